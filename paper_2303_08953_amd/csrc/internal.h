@@ -1,0 +1,193 @@
+// Internal declarations shared by the HIP sources of the s-step GMRES
+// library (gfx950, wave64).  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/sgm.h"
+
+namespace sgm {
+
+constexpr int kWave = 64;       // CDNA wavefront width
+constexpr int kSlice = 64;      // SELL-C slice height = one wavefront
+constexpr int kLdAlign = 64;    // leading dimensions are multiples of this
+constexpr int kSmallLds = 128;  // small FP64 matrices up to this size in LDS
+
+// ------------------------------------------------------------------ errors
+struct Error {
+  sgm_status st;
+  std::string msg;
+};
+void set_error(const std::string& m);
+const char* last_error();
+
+#define SGM_HIP(call)                                                      \
+  do {                                                                     \
+    hipError_t e_ = (call);                                                \
+    if (e_ != hipSuccess)                                                  \
+      throw ::sgm::Error{SGM_EHIP, std::string(#call) + ": " +             \
+                                       hipGetErrorString(e_)};             \
+  } while (0)
+
+#define SGM_CHECK_LAUNCH() SGM_HIP(hipGetLastError())
+
+#define SGM_REQUIRE(cond, msg)                                             \
+  do {                                                                     \
+    if (!(cond)) throw ::sgm::Error{SGM_EINVAL, (msg)};                    \
+  } while (0)
+
+inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------------ matrix
+// SELL-C sparse layout with C = 64 (one wavefront per slice of 64 rows).
+// Slice s covers rows [64 s, 64 s + 64); its entries sit at
+// ptr[s] + w * 64 + lane for w < width[s]; padding has val 0 and a column
+// index that is already being read by the same lane (no extra traffic).
+struct Sell {
+  int64_t n = 0;
+  int64_t nslices = 0;
+  int64_t nnz_padded = 0;
+  int64_t* ptr = nullptr;   // [nslices + 1]
+  int32_t* width = nullptr; // [nslices]
+  int32_t* col = nullptr;   // [nnz_padded]
+  int64_t* src = nullptr;   // [nnz_padded] CSR index of each entry, -1 = pad
+  double* val64 = nullptr;  // [nnz_padded]
+  float* val32 = nullptr;   // [nnz_padded]
+};
+
+struct Matrix {
+  int64_t n = 0, nnz = 0;
+  int32_t* row_ptr = nullptr;  // CSR copy (device)
+  int32_t* col = nullptr;
+  int32_t* row_of = nullptr;   // row index of every nonzero
+  double* val = nullptr;       // current values, CSR order
+  double* diag = nullptr;      // [n]
+  Sell fwd;                    // A
+  Sell trn;                    // A^T
+  // Jacobi-scaled value copies (A D^{-1}), built on demand inside a solve's
+  // workspace; nothing cached here.
+};
+
+Matrix* matrix_create(int64_t n, int64_t nnz, const int32_t* row_ptr,
+                      const int32_t* col, const double* val, hipStream_t st);
+void matrix_update_values(Matrix* M, const double* val, hipStream_t st);
+void matrix_destroy(Matrix* M);
+
+void sell_build(Sell& S, int64_t n, const int32_t* row_ptr,
+                const int32_t* col, const int32_t* perm_or_null,
+                hipStream_t st);
+void sell_fill_values(const Sell& S, const double* csr_val, hipStream_t st);
+void sell_free(Sell& S);
+void matrix_extract_diag(Matrix& M, hipStream_t st);
+
+// ------------------------------------------------------------------ SpMV
+enum SpmvEpi { EPI_PLAIN = 0, EPI_MPK = 1, EPI_RESID = 2 };
+
+// y = A x on SELL values `val` (float64 or float32); scale[] (optional,
+// per column) multiplies the value: A D^{-1} when scale = 1/diag.
+template <typename T>
+void spmv_plain(const Sell& S, const T* val, const T* x, T* y,
+                hipStream_t st);
+// y = ((A x) - theta x - delta xprev) / gamma with (theta, gamma, delta) =
+// rec[3 j .. 3 j + 2] read on the device.
+template <typename T>
+void spmv_mpk(const Sell& S, const T* val, const T* x, const T* xprev, T* y,
+              const double* rec, int j, hipStream_t st);
+// r = b - A x (float64) and per-block partial sums of r^2 into part[];
+// returns the number of partials written.
+int64_t spmv_resid(const Sell& S, const double* val, const double* x,
+                   const double* b, double* r, double* part, hipStream_t st);
+int64_t resid_partials(const Sell& S);
+
+// ------------------------------------------------------------------ vectors
+// out[0] = sqrt(sum part[0..np)) (deterministic order).
+void reduce_norm(const double* part, int64_t np, double* out, hipStream_t st);
+// q = (T)(r / *beta) for rows < n, zero for rows n..ld.
+template <typename T>
+void scale_into(const double* r, const double* beta, T* q, int64_t n,
+                int64_t ld, hipStream_t st);
+// zero rows n..ld-1 of columns [0, ncols) of a column-major matrix
+template <typename T>
+void zero_pad_rows(T* Q, int64_t n, int64_t ld, int ncols, hipStream_t st);
+void jacobi_values(const Matrix& M, const Sell& S, double* v64, float* v32,
+                   hipStream_t st);
+void vec_scale_div(double* x, const double* d, int64_t n, bool divide,
+                   hipStream_t st);
+void grad_vals(const Matrix& M, const double* lam, const double* x,
+               double* g, hipStream_t st);
+void cast_f64_f32(const double* a, float* b, int64_t n, hipStream_t st);
+void copy_f64(const double* a, double* b, int64_t n, hipStream_t st);
+
+// ------------------------------------------------------------------ tall-skinny
+// Partial-sum scratch for the grid reductions.
+struct Partials {
+  double* buf = nullptr;
+  int64_t cap = 0;  // doubles
+};
+
+// C(ma x nb, ld ldc, float64) = A(:, 0:ma)^T B(:, 0:nb) over rows [0, nrows).
+// ncount (device, may be NULL) masks B's columns: only min(nb, *ncount) are
+// used (the rest of C is written as zero).
+template <typename T>
+void gemm_tn(const T* A, int64_t lda, int ma, const T* B, int64_t ldb,
+             int nb, const int* ncount, int64_t nrows, double* C, int ldc,
+             Partials& P, hipStream_t st);
+
+// B(:, 0:nc) -= A(:, 0:ka) M(0:ka, 0:nc) (M float64, column-major, ld ldm)
+// and, when G is not NULL, G(nc x nc, ld ldg) = B^T B after the update.
+// ncount (device, may be NULL) limits nc to min(nc, *ncount).
+template <typename T>
+void update_gram(const T* A, int64_t lda, int ka, T* B, int64_t ldb, int nc,
+                 const double* M, int ldm, const int* ncount, int64_t nrows,
+                 double* G, int ldg, Partials& P, hipStream_t st);
+
+// B(:, 0:p) = B(:, 0:p) Rinv(0:p, 0:p) in place (Rinv upper triangular,
+// float64, ld ldr), p = min(s, *pcount).
+template <typename T>
+void trsm_inv(T* B, int64_t ldb, int s, const double* Rinv, int ldr,
+              const int* pcount, int64_t nrows, hipStream_t st);
+
+// x(0:n) += scale * Q(:, 0:k) y(0:k), x float64, Q float64/float32,
+// k read from kdev, scale read from sdev (NULL = 1).
+template <typename T>
+void gemv_update(const T* Q, int64_t ldq, const double* y, const int* kdev,
+                 int kmax, const double* sdev, double* x, int64_t n,
+                 hipStream_t st);
+
+// ------------------------------------------------------------------ small FP64
+// Control block shared by the single-workgroup kernels of one block.
+enum Ctrl {
+  C_P1 = 0, C_P2, C_PH, C_BREAK, C_KDONE, C_CONV, C_BAD, C_NCTRL
+};
+
+void pchol_ice(const double* G, int ldg, int smax, const int* s_dev,
+               double omega, double* R, double* Rinv, int ldr, int* p_out,
+               double* scratch, hipStream_t st);
+void combine_r(const double* W, int ldw, const double* R2, int ldr2,
+               const double* Z, const double* Zt, int ldz, int i,
+               int* ctrl, double* Rtop, int ldt, double* Rkk, int ldk,
+               hipStream_t st);
+void hess_givens(double* Hraw, double* Hr, int ldh, double* cs, double* sn,
+                 double* g, int nb, const double* Rtop, int ldt,
+                 const double* Rkk, int ldk, const double* rec, int n_rec,
+                 const double* beta0, double tol, int* ctrl, double* res_out,
+                 double* scratch, hipStream_t st);
+void back_solve(const double* Hr, int ldh, const double* g, const int* kdev,
+                int kmax, double* y, hipStream_t st);
+void givens_init(double* g, int m, const double* beta, hipStream_t st);
+
+// Ritz values, Leja order, recurrence records, estimator.
+void hqr_eigen(const double* H, int ldh, int m0, double* wr, double* wi,
+               double* scratch, int* status, hipStream_t st);
+void leja_records(const double* wr, const double* wi, int m0, int basis,
+                  double eps, double omega_est, double* ritz_out,
+                  double* rec, int* info_out, double* scratch,
+                  hipStream_t st);
+size_t shifts_scratch_doubles(int m0);
+
+}  // namespace sgm

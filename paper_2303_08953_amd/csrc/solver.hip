@@ -1,0 +1,980 @@
+// Host engine of the adaptive s-step GMRES (Alg. 4 with restarts, the Ritz
+// pre-phase and estimator of Secs. 3.4-3.5, float32 inner cycles inside
+// float64 refinement) and the C ABI.  Every arithmetic step runs in the HIP
+// kernels of this library; the host only sequences launches, carves the
+// caller's workspace and reads back the accepted block size and the
+// convergence flags once per block.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace sgm {
+
+thread_local std::string g_last_error;
+void set_error(const std::string& m) { g_last_error = m; }
+const char* last_error() { return g_last_error.c_str(); }
+
+namespace {
+
+// ------------------------------------------------------------------ arena
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  template <typename T>
+  T* take(int64_t count) {
+    off = (size_t)round_up((int64_t)off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * (size_t)(count > 0 ? count : 1);
+    return p;
+  }
+};
+
+struct Work {
+  void* Q = nullptr;
+  double* r = nullptr;
+  double* jac64 = nullptr;
+  float* jac32 = nullptr;
+  Partials P;
+  double *W = nullptr, *G = nullptr, *Z = nullptr, *Zinv = nullptr;
+  double *R2 = nullptr, *G2 = nullptr, *Zt = nullptr, *Ztinv = nullptr;
+  double *Rtop = nullptr, *Rkk = nullptr;
+  double *Hraw = nullptr, *Hr = nullptr, *cs = nullptr, *sn = nullptr;
+  double *g = nullptr, *y = nullptr, *res_blk = nullptr;
+  double *rec = nullptr, *mono = nullptr;
+  double *wr = nullptr, *wi = nullptr, *ritz = nullptr;
+  double *hqr_scr = nullptr, *leja_scr = nullptr, *pchol_scr = nullptr;
+  double* scal = nullptr;  // 0 beta0, 1 beta (current), 2 one
+  int* ctrl = nullptr;     // C_NCTRL
+  int* info = nullptr;     // 0 hqr status, 1..3 leja info
+  int64_t ld = 0;
+  int ldw = 0, lds = 0, ldh = 0;
+};
+
+int64_t part_cap(int m, int smax) {
+  int64_t a = (int64_t)1 << 22;
+  int64_t b = (int64_t)16 * (m + 1) * smax;
+  return a > b ? a : b;
+}
+
+void layout(Arena& a, Work& w, int64_t n, int64_t sell_nnz, int m, int smax,
+            int nshift_max, bool fp32, bool jacobi) {
+  w.ld = round_up(n, kLdAlign);
+  w.ldw = m + 1;
+  w.lds = smax;
+  w.ldh = m + 1;
+  if (fp32)
+    w.Q = a.take<float>(w.ld * (m + 2));
+  else
+    w.Q = a.take<double>(w.ld * (m + 2));
+  w.r = a.take<double>(w.ld);
+  if (jacobi) {
+    w.jac64 = a.take<double>(sell_nnz);
+    w.jac32 = a.take<float>(sell_nnz);
+  }
+  w.P.cap = part_cap(m, smax);
+  w.P.buf = a.take<double>(w.P.cap);
+  const int64_t ws = (int64_t)w.ldw * smax, ss = (int64_t)smax * smax;
+  w.W = a.take<double>(ws);
+  w.R2 = a.take<double>(ws);
+  w.Rtop = a.take<double>(ws);
+  w.G = a.take<double>(ss);
+  w.G2 = a.take<double>(ss);
+  w.Z = a.take<double>(ss);
+  w.Zinv = a.take<double>(ss);
+  w.Zt = a.take<double>(ss);
+  w.Ztinv = a.take<double>(ss);
+  w.Rkk = a.take<double>(ss);
+  w.Hraw = a.take<double>((int64_t)w.ldh * m);
+  w.Hr = a.take<double>((int64_t)w.ldh * m);
+  w.cs = a.take<double>(m);
+  w.sn = a.take<double>(m);
+  w.g = a.take<double>(m + 1);
+  w.y = a.take<double>(m + 1);
+  w.res_blk = a.take<double>(smax + 1);
+  const int nr = nshift_max > 0 ? nshift_max : 1;
+  w.rec = a.take<double>(3 * nr);
+  w.mono = a.take<double>(4);
+  w.wr = a.take<double>(nr);
+  w.wi = a.take<double>(nr);
+  w.ritz = a.take<double>(2 * nr);
+  w.hqr_scr = a.take<double>((int64_t)nr * nr);
+  w.leja_scr = a.take<double>((int64_t)shifts_scratch_doubles(nr));
+  w.pchol_scr = a.take<double>(ss);
+  w.scal = a.take<double>(8);
+  w.ctrl = a.take<int>(C_NCTRL + 1);
+  w.info = a.take<int>(8);
+}
+
+// pinned host mirror for the per-block readback
+struct HostMirror {
+  int* ctrl = nullptr;
+  double* res = nullptr;
+  double* scal = nullptr;
+};
+
+struct Handle {
+  Matrix* M = nullptr;
+  void* pinned = nullptr;  // hipHostMalloc'd readback area
+  size_t pinned_bytes = 0;
+};
+
+constexpr size_t kPinnedBytes = 64 * 1024;
+
+double unit_roundoff(bool fp32) {
+  return fp32 ? std::ldexp(1.0, -24) : std::ldexp(1.0, -53);
+}
+
+double default_omega(bool fp32) { return 0.1 / std::sqrt(unit_roundoff(fp32)); }
+
+using Clock = std::chrono::steady_clock;
+double ms_since(Clock::time_point t) {
+  return std::chrono::duration<double, std::milli>(Clock::now() - t).count();
+}
+
+// ------------------------------------------------------------------ block
+// Block orthogonalisation of V = Q(:, nb : nb+s-1) against Q(:, 0 : nb-1):
+// BCGS2 with two partial CholQR passes (Alg. 4 lines 5-17).  The accepted
+// sizes stay on the device (ctrl[C_P1], ctrl[C_P2]); later kernels read
+// them, so the sequence needs no host synchronisation.
+template <typename T>
+void orth_block(T* Q, int64_t ld, int64_t nrows, int nb, int s, double omega,
+                Work& w, hipStream_t st) {
+  T* V = Q + (int64_t)nb * ld;
+  int* p1 = w.ctrl + C_P1;
+  int* p2 = w.ctrl + C_P2;
+  // first BCGS: W = Q^T V; V -= Q W; G = V^T V
+  gemm_tn<T>(Q, ld, nb, V, ld, s, nullptr, nrows, w.W, w.ldw, w.P, st);
+  update_gram<T>(Q, ld, nb, V, ld, s, w.W, w.ldw, nullptr, nrows, w.G, w.lds,
+                 w.P, st);
+  // first partial CholQR: p1, Z; V(:, 0:p1) = V Z^{-1}
+  pchol_ice(w.G, w.lds, s, nullptr, omega, w.Z, w.Zinv, w.lds, p1,
+            w.pchol_scr, st);
+  trsm_inv<T>(V, ld, s, w.Zinv, w.lds, p1, nrows, st);
+  // second BCGS on the p1 accepted columns
+  gemm_tn<T>(Q, ld, nb, V, ld, s, p1, nrows, w.R2, w.ldw, w.P, st);
+  update_gram<T>(Q, ld, nb, V, ld, s, w.R2, w.ldw, p1, nrows, w.G2, w.lds,
+                 w.P, st);
+  // second partial CholQR: p2, Zt; V(:, 0:p2) = V Zt^{-1}
+  pchol_ice(w.G2, w.lds, s, p1, omega, w.Zt, w.Ztinv, w.lds, p2, w.pchol_scr,
+            st);
+  trsm_inv<T>(V, ld, s, w.Ztinv, w.lds, p2, nrows, st);
+  combine_r(w.W, w.ldw, w.R2, w.ldw, w.Z, w.Zt, w.lds, nb, w.ctrl, w.Rtop,
+            w.ldw, w.Rkk, w.lds, st);
+}
+
+struct Shifts {
+  bool known = false;
+  std::vector<double> rec;  // host copy, 3 per step
+  int n_rec = 0;
+  int s_init = 1;
+  int s0 = 0;
+  int hits = 0;
+};
+
+struct Result {
+  int iters = 0, restarts = 0, outer = 0;
+  double rel_true = 1.0, rel_est = 1.0;
+  sgm_status status = SGM_NOT_CONVERGED;
+  std::vector<double> res_hist;
+  std::vector<int> s_hist;
+  double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int s0 = 0, s_init = 0, n_rec = 0, hits = 0;
+};
+
+template <typename T>
+struct Engine {
+  const Matrix& A;
+  const Sell& S;
+  const T* vals;        // values the inner cycles use (T precision)
+  const double* vals64; // float64 values for true residuals
+  Work& w;
+  HostMirror hm;
+  hipStream_t st;
+  int64_t n, ld;
+  int m;
+  double omega;
+  double eps;
+  const sgm_opts& o;
+  Shifts sh;
+  Result& res;
+  hipEvent_t ev[4];
+
+  Engine(const Matrix& A_, const Sell& S_, const T* v, const double* v64,
+         Work& w_, HostMirror hm_, hipStream_t st_, const sgm_opts& o_,
+         Result& r_)
+      : A(A_), S(S_), vals(v), vals64(v64), w(w_), hm(hm_), st(st_),
+        n(A_.n), ld(w_.ld), m(o_.restart), o(o_), res(r_) {
+    const bool f32 = sizeof(T) == 4;
+    omega = o.omega > 0 ? o.omega : default_omega(f32);
+    eps = unit_roundoff(f32);
+    for (auto& e : ev) SGM_HIP(hipEventCreate(&e));
+  }
+  ~Engine() {
+    for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+
+  T* Q() { return static_cast<T*>(w.Q); }
+  T* col(int j) { return Q() + (int64_t)j * ld; }
+
+  void set_monomial() {
+    const double mono[3] = {0.0, 1.0, 0.0};
+    SGM_HIP(hipMemcpyAsync(w.mono, mono, sizeof(mono), hipMemcpyHostToDevice,
+                           st));
+  }
+
+  // Shifts from user-given Ritz values (skips the pre-phase).
+  void shifts_from_host(const double* pairs, int ns) {
+    SGM_HIP(hipMemcpyAsync(w.ritz, pairs, sizeof(double) * 2 * ns,
+                           hipMemcpyHostToDevice, st));
+    std::vector<double> re(ns), im(ns);
+    for (int k = 0; k < ns; ++k) {
+      re[k] = pairs[2 * k];
+      im[k] = pairs[2 * k + 1];
+    }
+    SGM_HIP(hipMemcpyAsync(w.wr, re.data(), sizeof(double) * ns,
+                           hipMemcpyHostToDevice, st));
+    SGM_HIP(hipMemcpyAsync(w.wi, im.data(), sizeof(double) * ns,
+                           hipMemcpyHostToDevice, st));
+    SGM_HIP(hipStreamSynchronize(st));
+    finish_shifts(ns, false);
+  }
+
+  // Ritz values of the pre-phase Hessenberg H(0:m0, 0:m0), Leja order,
+  // recurrence records and (scaled Newton) the estimator's s0*.
+  void compute_shifts(int m0) {
+    if (m0 <= 0) {
+      // breakdown before any column: a single neutral record
+      sh.rec = {0.0, 1.0, 0.0};
+      sh.n_rec = 1;
+      SGM_HIP(hipMemcpyAsync(w.rec, sh.rec.data(), sizeof(double) * 3,
+                             hipMemcpyHostToDevice, st));
+      sh.known = true;
+      sh.s_init = o.s_max;
+      return;
+    }
+    hqr_eigen(w.Hraw, w.ldh, m0, w.wr, w.wi, w.hqr_scr, w.info, st);
+    finish_shifts(m0, true);
+  }
+
+  void finish_shifts(int m0, bool check_hqr) {
+    const bool scaled = o.basis == SGM_BASIS_SCALED_NEWTON;
+    const double om_est =
+        (scaled && o.use_estimator)
+            ? (o.omega_est > 0 ? o.omega_est : default_omega(sizeof(T) == 4))
+            : 0.0;
+    leja_records(w.wr, w.wi, m0, (int)o.basis, eps, om_est, w.ritz, w.rec,
+                 w.info + 1, w.leja_scr, st);
+    int info[4] = {0, 0, 0, 0};
+    SGM_HIP(hipMemcpyAsync(info, w.info, sizeof(int) * 4,
+                           hipMemcpyDeviceToHost, st));
+    sh.rec.assign(3 * m0, 0.0);
+    SGM_HIP(hipMemcpyAsync(sh.rec.data(), w.rec, sizeof(double) * 3 * m0,
+                           hipMemcpyDeviceToHost, st));
+    SGM_HIP(hipStreamSynchronize(st));
+    if ((check_hqr && info[0] != 0) || info[3] != 0)
+      throw Error{SGM_ENUMERIC, "Ritz values: QR iteration failed or "
+                                "non-finite values"};
+    sh.known = true;
+    sh.n_rec = m0;
+    sh.s0 = info[1];
+    sh.hits = info[2];
+    sh.s_init = o.s_max;
+    if (scaled && o.use_estimator && sh.s0 > 0)
+      sh.s_init = std::max(1, std::min(o.s_max, sh.s0));
+  }
+
+  struct BlockOut {
+    int p2, ph, brk, kdone, conv, bad;
+  };
+
+  // One s-step block: MPK, BCGS2 + partial CholQR2, Hessenberg recovery,
+  // Givens and the convergence test; one host synchronisation at the end.
+  BlockOut block(int nb, int s_eff, bool mono, const double* beta0,
+                 double tol) {
+    const double* rec = mono ? w.mono : w.rec;
+    const int nrec = mono ? 1 : sh.n_rec;
+    SGM_HIP(hipEventRecord(ev[0], st));
+    for (int j = 0; j < s_eff; ++j) {
+      const int q = j % nrec;
+      const double delta = mono ? 0.0 : sh.rec[3 * q + 2];
+      const T* xprev = (j >= 1 && delta != 0.0) ? col(nb - 2 + j) : nullptr;
+      spmv_mpk<T>(S, vals, col(nb - 1 + j), xprev, col(nb + j), rec, q, st);
+    }
+    SGM_HIP(hipEventRecord(ev[1], st));
+    orth_block<T>(Q(), ld, ld, nb, s_eff, omega, w, st);
+    SGM_HIP(hipEventRecord(ev[2], st));
+    hess_givens(w.Hraw, w.Hr, w.ldh, w.cs, w.sn, w.g, nb, w.Rtop, w.ldw,
+                w.Rkk, w.lds, rec, nrec, beta0, tol, w.ctrl, w.res_blk,
+                nullptr, st);
+    SGM_HIP(hipEventRecord(ev[3], st));
+    SGM_HIP(hipMemcpyAsync(hm.ctrl, w.ctrl, sizeof(int) * C_NCTRL,
+                           hipMemcpyDeviceToHost, st));
+    SGM_HIP(hipMemcpyAsync(hm.res, w.res_blk, sizeof(double) * s_eff,
+                           hipMemcpyDeviceToHost, st));
+    SGM_HIP(hipStreamSynchronize(st));
+    float t01 = 0, t12 = 0, t23 = 0;
+    SGM_HIP(hipEventElapsedTime(&t01, ev[0], ev[1]));
+    SGM_HIP(hipEventElapsedTime(&t12, ev[1], ev[2]));
+    SGM_HIP(hipEventElapsedTime(&t23, ev[2], ev[3]));
+    res.t[2] += t01;
+    res.t[3] += t12;
+    res.t[4] += t23;
+    BlockOut b;
+    b.p2 = hm.ctrl[C_P2];
+    b.ph = hm.ctrl[C_PH];
+    b.brk = hm.ctrl[C_BREAK];
+    b.kdone = hm.ctrl[C_KDONE];
+    b.conv = hm.ctrl[C_CONV];
+    b.bad = hm.ctrl[C_BAD];
+    return b;
+  }
+
+  // One restart cycle from Q(:, 0) (already the normalised residual) with
+  // g = beta_dev e_1.  Returns the number of Hessenberg columns and leaves
+  // y in w.y.  res_scale converts the estimates to the caller's reference.
+  int cycle(const double* beta_dev, const double* beta0_dev, double tol,
+            bool prephase_only, double res_scale, bool* conv_out) {
+    SGM_HIP(hipMemsetAsync(w.Hraw, 0, sizeof(double) * w.ldh * m, st));
+    givens_init(w.g, m, beta_dev, st);
+    const int m0 = sh.known ? 0 : std::min(o.s_max, m);
+    const int last = prephase_only ? m0 : m;
+    int nb = 1, k = 0;
+    bool conv = false;
+    int s = sh.s_init;
+    auto t_pre = Clock::now();
+    bool timing_pre = !sh.known;
+    while (nb <= last && !conv) {
+      if (!sh.known && nb > m0) {
+        compute_shifts(nb - 1);
+        s = sh.s_init;
+        res.t[1] += ms_since(t_pre);
+        timing_pre = false;
+      }
+      const bool in_pre = !sh.known;
+      const int s_eff = std::min(in_pre ? 1 : s, m + 1 - nb);
+      BlockOut b = block(nb, s_eff, in_pre || o.basis == SGM_BASIS_MONOMIAL,
+                         beta0_dev, prephase_only ? -1.0 : tol);
+      if (b.bad) throw Error{SGM_ENUMERIC, "non-finite residual estimate"};
+      if (!prephase_only) {
+        for (int j = 0; j < b.kdone; ++j)
+          res.res_hist.push_back(hm.res[j] * res_scale);
+        res.s_hist.push_back(b.brk ? 0 : b.p2);
+        if (b.kdone > 0) res.rel_est = hm.res[b.kdone - 1] * res_scale;
+      }
+      k = nb - 1 + b.kdone;
+      if (b.brk) {
+        conv = true;
+        break;
+      }
+      if (b.conv) conv = true;
+      nb += b.p2;
+      if (!in_pre) s = b.p2;
+    }
+    if (!sh.known) {
+      compute_shifts(k);
+      if (timing_pre) res.t[1] += ms_since(t_pre);
+    }
+    if (conv_out) *conv_out = conv;
+    if (prephase_only) return 0;
+    back_solve(w.Hr, w.ldh, w.g, nullptr, k, w.y, st);
+    return k;
+  }
+};
+
+// ------------------------------------------------------------------ solve
+template <typename T>
+void run_solve(Handle* h, const double* b, const double* x0, double* x,
+               const sgm_opts& o, Work& w, hipStream_t st, Result& R) {
+  const Matrix& A = *h->M;
+  const Sell& S = o.transpose ? A.trn : A.fwd;
+  const int64_t n = A.n;
+  const bool jac = o.precond == SGM_PRECOND_JACOBI;
+  const bool f32 = sizeof(T) == 4;
+  auto t0 = Clock::now();
+  HostMirror hm;
+  hm.ctrl = static_cast<int*>(h->pinned);
+  hm.res = reinterpret_cast<double*>(static_cast<char*>(h->pinned) + 256);
+  hm.scal = reinterpret_cast<double*>(static_cast<char*>(h->pinned) + 128);
+  const double* v64 = S.val64;
+  const float* v32 = S.val32;
+  if (jac) {
+    jacobi_values(A, S, w.jac64, w.jac32, st);
+    v64 = w.jac64;
+    v32 = w.jac32;
+  }
+  const T* vT;
+  if constexpr (sizeof(T) == 4) vT = v32; else vT = v64;
+  // x = x0 (or 0); with Jacobi the iterate is u = D x
+  if (x0 == nullptr)
+    SGM_HIP(hipMemsetAsync(x, 0, sizeof(double) * n, st));
+  else if (x0 != x)
+    SGM_HIP(hipMemcpyAsync(x, x0, sizeof(double) * n, hipMemcpyDeviceToDevice,
+                           st));
+  if (jac) vec_scale_div(x, A.diag, n, false, st);
+  zero_pad_rows<T>(static_cast<T*>(w.Q), n, w.ld, o.restart + 2, st);
+  const double one = 1.0;
+  SGM_HIP(hipMemcpyAsync(w.scal + 2, &one, sizeof(double),
+                         hipMemcpyHostToDevice, st));
+  Engine<T> E(A, S, vT, v64, w, hm, st, o, R);
+  E.set_monomial();
+  if (o.basis == SGM_BASIS_MONOMIAL) {
+    E.sh.known = true;
+    E.sh.rec = {0.0, 1.0, 0.0};
+    E.sh.n_rec = 1;
+    E.sh.s_init = o.s_max;
+    SGM_HIP(hipMemcpyAsync(w.rec, E.sh.rec.data(), sizeof(double) * 3,
+                           hipMemcpyHostToDevice, st));
+  } else if (o.shifts_host != nullptr && o.n_shifts > 0) {
+    E.shifts_from_host(o.shifts_host, o.n_shifts);
+  }
+  // r0 = b - A x0, beta0
+  const int64_t np = spmv_resid(S, v64, x, b, w.r, w.P.buf, st);
+  reduce_norm(w.P.buf, np, w.scal + 0, st);
+  SGM_HIP(hipMemcpyAsync(hm.scal, w.scal, sizeof(double), hipMemcpyDeviceToHost,
+                         st));
+  SGM_HIP(hipStreamSynchronize(st));
+  const double beta0 = hm.scal[0];
+  R.t[0] = ms_since(t0);
+  auto finish = [&]() {
+    if (jac) vec_scale_div(x, A.diag, n, true, st);
+    SGM_HIP(hipStreamSynchronize(st));
+    R.t[7] = ms_since(t0);
+  };
+  if (beta0 == 0.0) {
+    R.rel_true = 0.0;
+    R.status = SGM_OK;
+    finish();
+    return;
+  }
+  if (!std::isfinite(beta0)) {
+    R.status = SGM_ENUMERIC;
+    finish();
+    throw Error{SGM_ENUMERIC, "initial residual is not finite"};
+  }
+  SGM_HIP(hipMemcpyAsync(w.scal + 1, w.scal + 0, sizeof(double),
+                         hipMemcpyDeviceToDevice, st));
+  double beta = beta0;
+  auto true_residual = [&]() {
+    auto tc = Clock::now();
+    const int64_t np2 = spmv_resid(S, v64, x, b, w.r, w.P.buf, st);
+    reduce_norm(w.P.buf, np2, w.scal + 1, st);
+    SGM_HIP(hipMemcpyAsync(hm.scal + 1, w.scal + 1, sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+    SGM_HIP(hipStreamSynchronize(st));
+    R.t[5] += ms_since(tc);
+    return hm.scal[1];
+  };
+  if (!f32) {
+    if (!E.sh.known && !o.ritz_reuse) {
+      scale_into<T>(w.r, w.scal + 1, E.col(0), n, w.ld, st);
+      E.cycle(w.scal + 1, w.scal + 0, o.tol, true, 1.0, nullptr);
+    }
+    for (;;) {
+      scale_into<T>(w.r, w.scal + 1, E.col(0), n, w.ld, st);
+      const int k = E.cycle(w.scal + 1, w.scal + 0, o.tol, false, 1.0, nullptr);
+      auto tc = Clock::now();
+      if (k > 0) gemv_update<T>(E.Q(), w.ld, w.y, nullptr, k, nullptr, x, n, st);
+      R.t[5] += ms_since(tc);
+      R.iters += k;
+      beta = true_residual();
+      R.rel_true = beta / beta0;
+      if (!std::isfinite(R.rel_true)) {
+        finish();
+        throw Error{SGM_ENUMERIC, "true residual is not finite"};
+      }
+      if (R.rel_true <= o.tol) {
+        R.status = SGM_OK;
+        break;
+      }
+      if (R.restarts >= o.max_restarts || k == 0) break;
+      R.restarts += 1;
+    }
+  } else {
+    // float32 inner cycles inside float64 iterative refinement
+    auto tir = Clock::now();
+    if (!E.sh.known && !o.ritz_reuse) {
+      scale_into<T>(w.r, w.scal + 1, E.col(0), n, w.ld, st);
+      E.cycle(w.scal + 2, w.scal + 2, o.inner_tol, true, 1.0, nullptr);
+    }
+    R.rel_true = 1.0;
+    while (R.outer < o.max_outer) {
+      scale_into<T>(w.r, w.scal + 1, E.col(0), n, w.ld, st);
+      const double scale = beta / beta0;
+      const int k =
+          E.cycle(w.scal + 2, w.scal + 2, o.inner_tol, false, scale, nullptr);
+      R.outer += 1;
+      R.iters += k;
+      if (k > 0)
+        gemv_update<T>(E.Q(), w.ld, w.y, nullptr, k, w.scal + 1, x, n, st);
+      beta = true_residual();
+      R.rel_true = beta / beta0;
+      if (!std::isfinite(R.rel_true)) {
+        finish();
+        throw Error{SGM_ENUMERIC, "true residual is not finite"};
+      }
+      if (R.rel_true <= o.tol) {
+        R.status = SGM_OK;
+        break;
+      }
+      if (k == 0) break;
+    }
+    R.restarts = R.outer > 0 ? R.outer - 1 : 0;
+    R.t[6] = ms_since(tir);
+  }
+  finish();
+  R.s0 = E.sh.s0;
+  R.s_init = E.sh.s_init;
+  R.n_rec = E.sh.n_rec;
+  R.hits = E.sh.hits;
+}
+
+}  // namespace
+}  // namespace sgm
+
+// ====================================================================== ABI
+namespace {
+
+using namespace sgm;
+
+Handle* handle(sgm_matrix A) { return reinterpret_cast<Handle*>(A); }
+
+#define SGM_API_BEGIN try {
+#define SGM_API_END                                                        \
+  }                                                                        \
+  catch (const Error& e) {                                                 \
+    set_error(e.msg);                                                      \
+    return e.st;                                                           \
+  }                                                                        \
+  catch (const std::exception& e) {                                        \
+    set_error(e.what());                                                   \
+    return SGM_EHIP;                                                       \
+  }                                                                        \
+  catch (...) {                                                            \
+    set_error("unknown error");                                            \
+    return SGM_EHIP;                                                       \
+  }
+
+void validate_opts(const sgm_opts* o) {
+  SGM_REQUIRE(o != nullptr, "opts is NULL");
+  SGM_REQUIRE(o->s_max >= 1 && o->s_max <= 256, "s_max must be in [1, 256]");
+  SGM_REQUIRE(o->restart >= 1 && o->restart <= 4096,
+              "restart must be in [1, 4096]");
+  SGM_REQUIRE(o->max_restarts >= 0, "max_restarts must be >= 0");
+  SGM_REQUIRE(o->tol > 0.0 && std::isfinite(o->tol), "tol must be > 0");
+  SGM_REQUIRE(o->precond == SGM_PRECOND_NONE || o->precond == SGM_PRECOND_JACOBI,
+              "unknown preconditioner");
+  SGM_REQUIRE(o->basis == SGM_BASIS_SCALED_NEWTON ||
+                  o->basis == SGM_BASIS_NEWTON ||
+                  o->basis == SGM_BASIS_MONOMIAL,
+              "unknown basis");
+  SGM_REQUIRE(o->precision == SGM_FP64 || o->precision == SGM_FP32_IR,
+              "unknown precision");
+  SGM_REQUIRE(o->omega >= 0.0 && o->omega_est >= 0.0,
+              "omega and omega_est must be >= 0");
+  if (o->precision == SGM_FP32_IR) {
+    SGM_REQUIRE(o->inner_tol > 0.0 && o->inner_tol < 1.0,
+                "inner_tol must be in (0, 1)");
+    SGM_REQUIRE(o->max_outer >= 1, "max_outer must be >= 1");
+  }
+  if (o->shifts_host != nullptr)
+    SGM_REQUIRE(o->n_shifts >= 1 && o->n_shifts <= 1024,
+                "n_shifts must be in [1, 1024]");
+}
+
+int nshift_max(const sgm_opts& o) {
+  if (o.shifts_host != nullptr) return o.n_shifts;
+  return std::min(o.s_max, o.restart);
+}
+
+size_t solve_ws_bytes(const Matrix& M, const sgm_opts& o) {
+  Arena a;
+  Work w;
+  const int64_t snnz = std::max(M.fwd.nnz_padded, M.trn.nnz_padded);
+  layout(a, w, M.n, snnz, o.restart, o.s_max, nshift_max(o),
+         o.precision == SGM_FP32_IR, o.precond == SGM_PRECOND_JACOBI);
+  return a.off + 256;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Workspace of the stand-alone block orthogonalisation.
+void block_layout(Arena& a, Work& w, int i, int s) {
+  w.ldw = std::max(i, 1);
+  w.lds = s;
+  w.P.cap = std::max<int64_t>((int64_t)1 << 22, (int64_t)16 * (i + 1) * s);
+  w.P.buf = a.take<double>(w.P.cap);
+  const int64_t ws = (int64_t)w.ldw * s, ss = (int64_t)s * s;
+  w.W = a.take<double>(ws);
+  w.R2 = a.take<double>(ws);
+  w.Rtop = a.take<double>(ws);
+  w.G = a.take<double>(ss);
+  w.G2 = a.take<double>(ss);
+  w.Z = a.take<double>(ss);
+  w.Zinv = a.take<double>(ss);
+  w.Zt = a.take<double>(ss);
+  w.Ztinv = a.take<double>(ss);
+  w.Rkk = a.take<double>(ss);
+  w.pchol_scr = a.take<double>(ss);
+  w.ctrl = a.take<int>(C_NCTRL + 1);
+}
+
+void shifts_layout(Arena& a, Work& w, int m0) {
+  w.wr = a.take<double>(m0);
+  w.wi = a.take<double>(m0);
+  w.ritz = a.take<double>(2 * m0);
+  w.rec = a.take<double>(3 * m0);
+  w.hqr_scr = a.take<double>((int64_t)m0 * m0);
+  w.leja_scr = a.take<double>((int64_t)shifts_scratch_doubles(m0));
+  w.info = a.take<int>(8);
+}
+
+}  // namespace
+
+extern "C" {
+
+sgm_status sgm_matrix_create(int64_t n, int64_t nnz, const int32_t* row_ptr,
+                             const int32_t* col, const double* val,
+                             void* stream, sgm_matrix* out) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(out != nullptr, "out is NULL");
+  *out = nullptr;
+  SGM_REQUIRE(n >= 1 && n < ((int64_t)1 << 31) - 64, "n out of range");
+  SGM_REQUIRE(nnz >= 0 && nnz < ((int64_t)1 << 31), "nnz out of range");
+  SGM_REQUIRE(row_ptr != nullptr, "row_ptr is NULL");
+  SGM_REQUIRE(nnz == 0 || (col != nullptr && val != nullptr),
+              "col/val is NULL");
+  Handle* h = new Handle();
+  try {
+    h->M = matrix_create(n, nnz, row_ptr, col, val, as_stream(stream));
+    SGM_HIP(hipHostMalloc(&h->pinned, kPinnedBytes, hipHostMallocDefault));
+    h->pinned_bytes = kPinnedBytes;
+  } catch (...) {
+    if (h->M) matrix_destroy(h->M);
+    delete h;
+    throw;
+  }
+  *out = reinterpret_cast<sgm_matrix>(h);
+  return SGM_OK;
+  SGM_API_END
+}
+
+sgm_status sgm_matrix_update_values(sgm_matrix A, const double* val,
+                                    void* stream) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(A != nullptr, "matrix is NULL");
+  SGM_REQUIRE(val != nullptr || handle(A)->M->nnz == 0, "val is NULL");
+  matrix_update_values(handle(A)->M, val, as_stream(stream));
+  return SGM_OK;
+  SGM_API_END
+}
+
+sgm_status sgm_matrix_destroy(sgm_matrix A) {
+  SGM_API_BEGIN
+  if (A == nullptr) return SGM_OK;
+  Handle* h = handle(A);
+  matrix_destroy(h->M);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  delete h;
+  return SGM_OK;
+  SGM_API_END
+}
+
+sgm_status sgm_matrix_info(sgm_matrix A, int64_t* n, int64_t* nnz,
+                           int64_t* sell_nnz) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(A != nullptr, "matrix is NULL");
+  const Matrix& M = *handle(A)->M;
+  if (n) *n = M.n;
+  if (nnz) *nnz = M.nnz;
+  if (sell_nnz) *sell_nnz = M.fwd.nnz_padded;
+  return SGM_OK;
+  SGM_API_END
+}
+
+sgm_status sgm_spmv(sgm_matrix A, int transpose, sgm_precision precision,
+                    const void* x, void* y, void* stream) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(A != nullptr && x != nullptr && y != nullptr, "NULL argument");
+  SGM_REQUIRE(precision == SGM_FP64 || precision == SGM_FP32_IR,
+              "unknown precision");
+  const Matrix& M = *handle(A)->M;
+  const Sell& S = transpose ? M.trn : M.fwd;
+  if (precision == SGM_FP64)
+    spmv_plain<double>(S, S.val64, static_cast<const double*>(x),
+                       static_cast<double*>(y), as_stream(stream));
+  else
+    spmv_plain<float>(S, S.val32, static_cast<const float*>(x),
+                      static_cast<float*>(y), as_stream(stream));
+  return SGM_OK;
+  SGM_API_END
+}
+
+void sgm_opts_default(sgm_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->s_max = 8;
+  o->restart = 64;
+  o->max_restarts = 100;
+  o->tol = 1e-10;
+  o->precond = SGM_PRECOND_NONE;
+  o->basis = SGM_BASIS_SCALED_NEWTON;
+  o->precision = SGM_FP64;
+  o->omega = 0.0;
+  o->omega_est = 0.0;
+  o->use_estimator = 1;
+  o->transpose = 0;
+  o->inner_tol = 1e-6;
+  o->max_outer = 200;
+  o->ritz_reuse = 1;
+  o->shifts_host = nullptr;
+  o->n_shifts = 0;
+}
+
+sgm_status sgm_workspace_size(sgm_matrix A, const sgm_opts* o,
+                              size_t* bytes) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(A != nullptr && bytes != nullptr, "NULL argument");
+  validate_opts(o);
+  *bytes = solve_ws_bytes(*handle(A)->M, *o);
+  return SGM_OK;
+  SGM_API_END
+}
+
+sgm_status sgm_solve(sgm_matrix A, const double* b, const double* x0,
+                     double* x, const sgm_opts* o, void* ws, size_t ws_bytes,
+                     void* stream, double* res_hist, int32_t res_cap,
+                     int32_t* s_hist, int32_t s_cap, sgm_info* info) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(A != nullptr, "matrix is NULL");
+  SGM_REQUIRE(b != nullptr && x != nullptr, "b or x is NULL");
+  validate_opts(o);
+  SGM_REQUIRE(res_cap >= 0 && s_cap >= 0, "negative history capacity");
+  Handle* h = handle(A);
+  const size_t need = solve_ws_bytes(*h->M, *o);
+  SGM_REQUIRE(ws != nullptr && ws_bytes >= need,
+              "workspace too small: need " + std::to_string(need) + " bytes");
+  SGM_REQUIRE(o->s_max + 1 <= (int)((kPinnedBytes - 256) / sizeof(double)),
+              "s_max too large");
+  Arena a;
+  a.base = reinterpret_cast<char*>(
+      round_up(reinterpret_cast<int64_t>(ws), 256));
+  Work w;
+  const int64_t snnz = std::max(h->M->fwd.nnz_padded, h->M->trn.nnz_padded);
+  layout(a, w, h->M->n, snnz, o->restart, o->s_max, nshift_max(*o),
+         o->precision == SGM_FP32_IR, o->precond == SGM_PRECOND_JACOBI);
+  Result R;
+  sgm_status st = SGM_OK;
+  std::string err;
+  try {
+    if (o->precision == SGM_FP64)
+      run_solve<double>(h, b, x0, x, *o, w, as_stream(stream), R);
+    else
+      run_solve<float>(h, b, x0, x, *o, w, as_stream(stream), R);
+    st = R.status;
+  } catch (const Error& e) {
+    st = e.st;
+    err = e.msg;
+  }
+  if (res_hist)
+    for (int32_t i = 0; i < res_cap && i < (int32_t)R.res_hist.size(); ++i)
+      res_hist[i] = R.res_hist[i];
+  if (s_hist)
+    for (int32_t i = 0; i < s_cap && i < (int32_t)R.s_hist.size(); ++i)
+      s_hist[i] = R.s_hist[i];
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->iters = R.iters;
+    info->restarts = R.restarts;
+    info->outer_iters = o->precision == SGM_FP32_IR ? R.outer : 0;
+    info->s0_est = R.s0;
+    info->s_init = R.s_init;
+    info->n_hist = (int32_t)R.res_hist.size();
+    info->n_blocks = (int32_t)R.s_hist.size();
+    info->n_shifts = R.n_rec;
+    info->gamma_guard_hits = R.hits;
+    info->rel_res_true = R.rel_true;
+    info->rel_res_est = R.rel_est;
+    for (int i = 0; i < 8; ++i) info->t_phase_ms[i] = R.t[i];
+  }
+  if (st < 0) set_error(err);
+  return st;
+  SGM_API_END
+}
+
+sgm_status sgm_grad_vals(sgm_matrix A, const double* lambda, const double* x,
+                         double* grad_val, void* stream) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(A != nullptr && lambda != nullptr && x != nullptr &&
+                  grad_val != nullptr,
+              "NULL argument");
+  grad_vals(*handle(A)->M, lambda, x, grad_val, as_stream(stream));
+  return SGM_OK;
+  SGM_API_END
+}
+
+sgm_status sgm_mpk(sgm_matrix A, int transpose, sgm_precision precision,
+                   void* Q, int64_t ldq, int32_t c, int32_t s,
+                   const double* records, int32_t n_rec, void* stream) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(A != nullptr && Q != nullptr && records != nullptr,
+              "NULL argument");
+  const Matrix& M = *handle(A)->M;
+  SGM_REQUIRE(ldq >= M.n && ldq % kLdAlign == 0,
+              "ldq must be >= n and a multiple of 64");
+  SGM_REQUIRE(c >= 0 && s >= 0 && n_rec >= 1, "bad c/s/n_rec");
+  SGM_REQUIRE(precision == SGM_FP64 || precision == SGM_FP32_IR,
+              "unknown precision");
+  const Sell& S = transpose ? M.trn : M.fwd;
+  hipStream_t st = as_stream(stream);
+  for (int j = 0; j < s; ++j) {
+    const int q = j % n_rec;
+    if (precision == SGM_FP64) {
+      double* B = static_cast<double*>(Q);
+      spmv_mpk<double>(S, S.val64, B + (int64_t)(c + j) * ldq,
+                       j >= 1 ? B + (int64_t)(c + j - 1) * ldq : nullptr,
+                       B + (int64_t)(c + j + 1) * ldq, records, q, st);
+    } else {
+      float* B = static_cast<float*>(Q);
+      spmv_mpk<float>(S, S.val32, B + (int64_t)(c + j) * ldq,
+                      j >= 1 ? B + (int64_t)(c + j - 1) * ldq : nullptr,
+                      B + (int64_t)(c + j + 1) * ldq, records, q, st);
+    }
+  }
+  return SGM_OK;
+  SGM_API_END
+}
+
+size_t sgm_block_ws_size(int64_t n_rows, int32_t i, int32_t s) {
+  (void)n_rows;
+  if (i < 1 || s < 1) return 0;
+  Arena a;
+  Work w;
+  block_layout(a, w, i, s);
+  return a.off + 256;
+}
+
+sgm_status sgm_block_orth(sgm_precision precision, int64_t n_rows, void* Q,
+                          int64_t ldq, int32_t i, int32_t s, double omega,
+                          void* ws, size_t ws_bytes, void* stream, int32_t* p,
+                          double* R_top, double* R_kk) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(Q != nullptr && p != nullptr, "NULL argument");
+  SGM_REQUIRE(n_rows >= 1 && ldq >= n_rows && ldq % kLdAlign == 0,
+              "ldq must be >= n_rows and a multiple of 64");
+  SGM_REQUIRE(i >= 1 && s >= 1 && s <= 256, "need i >= 1 and 1 <= s <= 256");
+  SGM_REQUIRE(precision == SGM_FP64 || precision == SGM_FP32_IR,
+              "unknown precision");
+  SGM_REQUIRE(omega >= 0.0, "omega must be >= 0");
+  const size_t need = sgm_block_ws_size(n_rows, i, s);
+  SGM_REQUIRE(ws != nullptr && ws_bytes >= need, "workspace too small");
+  Arena a;
+  a.base = reinterpret_cast<char*>(
+      round_up(reinterpret_cast<int64_t>(ws), 256));
+  Work w;
+  block_layout(a, w, i, s);
+  hipStream_t st = as_stream(stream);
+  const bool f32 = precision == SGM_FP32_IR;
+  const double om = omega > 0 ? omega : default_omega(f32);
+  if (f32)
+    orth_block<float>(static_cast<float*>(Q), ldq, ldq, i, s, om, w, st);
+  else
+    orth_block<double>(static_cast<double*>(Q), ldq, ldq, i, s, om, w, st);
+  int ctrl[C_NCTRL];
+  SGM_HIP(hipMemcpyAsync(ctrl, w.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost,
+                         st));
+  if (R_top)
+    SGM_HIP(hipMemcpyAsync(R_top, w.Rtop, sizeof(double) * (size_t)i * s,
+                           hipMemcpyDeviceToHost, st));
+  if (R_kk)
+    SGM_HIP(hipMemcpyAsync(R_kk, w.Rkk, sizeof(double) * (size_t)s * s,
+                           hipMemcpyDeviceToHost, st));
+  SGM_HIP(hipStreamSynchronize(st));
+  *p = ctrl[C_P2];
+  return SGM_OK;
+  SGM_API_END
+}
+
+size_t sgm_shifts_ws_size(int32_t m0) {
+  if (m0 < 1) return 0;
+  Arena a;
+  Work w;
+  shifts_layout(a, w, m0);
+  return a.off + 256;
+}
+
+sgm_status sgm_shifts(const double* H, int32_t ldh, int32_t m0,
+                      sgm_basis basis, double eps, double omega_est,
+                      void* ws, size_t ws_bytes, void* stream,
+                      double* ritz_re, double* ritz_im, double* records,
+                      int32_t* s0, int32_t* guard_hits) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(H != nullptr, "H is NULL");
+  SGM_REQUIRE(m0 >= 1 && m0 <= 1024 && ldh >= m0, "need 1 <= m0 <= 1024, ldh >= m0");
+  SGM_REQUIRE(eps > 0.0 && eps < 1.0, "eps must be in (0, 1)");
+  SGM_REQUIRE(omega_est >= 0.0, "omega_est must be >= 0");
+  SGM_REQUIRE(basis == SGM_BASIS_SCALED_NEWTON || basis == SGM_BASIS_NEWTON ||
+                  basis == SGM_BASIS_MONOMIAL,
+              "unknown basis");
+  const size_t need = sgm_shifts_ws_size(m0);
+  SGM_REQUIRE(ws != nullptr && ws_bytes >= need, "workspace too small");
+  Arena a;
+  a.base = reinterpret_cast<char*>(
+      round_up(reinterpret_cast<int64_t>(ws), 256));
+  Work w;
+  shifts_layout(a, w, m0);
+  hipStream_t st = as_stream(stream);
+  hqr_eigen(H, ldh, m0, w.wr, w.wi, w.hqr_scr, w.info, st);
+  leja_records(w.wr, w.wi, m0, (int)basis, eps,
+               basis == SGM_BASIS_SCALED_NEWTON ? omega_est : 0.0, w.ritz,
+               w.rec, w.info + 1, w.leja_scr, st);
+  int info[4];
+  std::vector<double> ritz(2 * (size_t)m0), rec(3 * (size_t)m0);
+  SGM_HIP(hipMemcpyAsync(info, w.info, sizeof(info), hipMemcpyDeviceToHost,
+                         st));
+  SGM_HIP(hipMemcpyAsync(ritz.data(), w.ritz, sizeof(double) * ritz.size(),
+                         hipMemcpyDeviceToHost, st));
+  SGM_HIP(hipMemcpyAsync(rec.data(), w.rec, sizeof(double) * rec.size(),
+                         hipMemcpyDeviceToHost, st));
+  SGM_HIP(hipStreamSynchronize(st));
+  if (ritz_re)
+    for (int k = 0; k < m0; ++k) ritz_re[k] = ritz[2 * k];
+  if (ritz_im)
+    for (int k = 0; k < m0; ++k) ritz_im[k] = ritz[2 * k + 1];
+  if (records) std::memcpy(records, rec.data(), sizeof(double) * rec.size());
+  if (s0) *s0 = info[1];
+  if (guard_hits) *guard_hits = info[2];
+  if (info[0] != 0 || info[3] != 0)
+    throw Error{SGM_ENUMERIC, "QR iteration failed or non-finite Ritz values"};
+  return SGM_OK;
+  SGM_API_END
+}
+
+const char* sgm_status_string(sgm_status s) {
+  switch (s) {
+    case SGM_OK: return "ok";
+    case SGM_NOT_CONVERGED: return "not converged";
+    case SGM_EINVAL: return "invalid argument";
+    case SGM_EHIP: return "HIP error";
+    case SGM_ENOMEM: return "out of device memory";
+    case SGM_ENUMERIC: return "numerical breakdown (NaN/Inf)";
+  }
+  return "unknown status";
+}
+
+const char* sgm_last_error(void) { return last_error(); }
+
+int sgm_device_ok(void) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, 0) != hipSuccess) return 0;
+  return std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 0;
+}
+
+}  // extern "C"

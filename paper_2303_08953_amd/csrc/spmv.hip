@@ -1,0 +1,257 @@
+// Sparse mat-vec on SELL-C-64 (one wavefront per 64-row slice, fully
+// coalesced value/index streams) with the epilogues the s-step cycle needs,
+// plus the small vector kernels around it.
+#include "internal.h"
+
+namespace sgm {
+
+namespace {
+
+constexpr int kSpmvBlock = 256;                    // 4 wavefronts
+constexpr int kSlicesPerBlock = kSpmvBlock / kWave;
+
+template <typename T, int EPI>
+__global__ __launch_bounds__(kSpmvBlock) void k_spmv(
+    const int64_t* __restrict__ ptr, const int32_t* __restrict__ width,
+    const int32_t* __restrict__ col, const T* __restrict__ val,
+    const T* __restrict__ x, const T* __restrict__ xprev, T* __restrict__ y,
+    const double* __restrict__ b, double* __restrict__ part, int64_t n,
+    int64_t nslices, const double* __restrict__ rec, int j) {
+  const int64_t s = (int64_t)blockIdx.x * kSlicesPerBlock + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int64_t r = s * kSlice + lane;
+  T sum = 0;
+  if (s < nslices) {
+    const int64_t base = ptr[s] + lane;
+    const int w = width[s];
+    int k = 0;
+    for (; k + 4 <= w; k += 4) {
+      const int64_t e = base + (int64_t)k * kSlice;
+      const int32_t c0 = col[e], c1 = col[e + kSlice], c2 = col[e + 2 * kSlice],
+                    c3 = col[e + 3 * kSlice];
+      const T v0 = val[e], v1 = val[e + kSlice], v2 = val[e + 2 * kSlice],
+              v3 = val[e + 3 * kSlice];
+      sum += v0 * x[c0];
+      sum += v1 * x[c1];
+      sum += v2 * x[c2];
+      sum += v3 * x[c3];
+    }
+    for (; k < w; ++k) {
+      const int64_t e = base + (int64_t)k * kSlice;
+      sum += val[e] * x[col[e]];
+    }
+  }
+  if constexpr (EPI == EPI_PLAIN) {
+    if (r < n) y[r] = sum;
+  } else if constexpr (EPI == EPI_MPK) {
+    if (r < n) {
+      const T theta = (T)rec[3 * j], gamma = (T)rec[3 * j + 1],
+              delta = (T)rec[3 * j + 2];
+      T v = sum - theta * x[r];
+      if (xprev != nullptr) v = v - delta * xprev[r];
+      y[r] = v / gamma;
+    }
+  } else {  // EPI_RESID (float64): r = b - A x, partial sums of r^2
+    double rr = 0.0;
+    if (r < n) {
+      rr = b[r] - (double)sum;
+      y[r] = (T)rr;
+    }
+    double q = rr * rr;
+    for (int off = kWave / 2; off > 0; off >>= 1) q += __shfl_xor(q, off);
+    __shared__ double red[kSlicesPerBlock];
+    if (lane == 0) red[threadIdx.x / kWave] = q;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kSlicesPerBlock; ++w) t += red[w];
+      part[blockIdx.x] = t;
+    }
+  }
+}
+
+inline unsigned spmv_grid(const Sell& S) {
+  return (unsigned)ceil_div(S.nslices, kSlicesPerBlock);
+}
+
+__global__ __launch_bounds__(1024) void k_reduce_norm(const double* part,
+                                                      int64_t np,
+                                                      double* out) {
+  __shared__ double red[1024];
+  double t = 0.0;
+  for (int64_t i = threadIdx.x; i < np; i += 1024) t += part[i];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sqrt(red[0]);
+}
+
+template <typename T>
+__global__ void k_scale_into(const double* r, const double* beta, T* q,
+                             int64_t n, int64_t ld) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= ld) return;
+  q[i] = i < n ? (T)(r[i] / beta[0]) : (T)0;
+}
+
+template <typename T>
+__global__ void k_zero_pad(T* Q, int64_t n, int64_t ld, int ncols) {
+  int64_t pad = ld - n;
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= pad * ncols) return;
+  int64_t c = t / pad, r = n + t % pad;
+  Q[c * ld + r] = (T)0;
+}
+
+__global__ void k_jacobi_values(const int64_t* src, const int32_t* col,
+                                int64_t m, const double* val,
+                                const double* diag, double* v64, float* v32) {
+  int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  int64_t k = src[e];
+  double v = k >= 0 ? val[k] / diag[col[e]] : 0.0;
+  v64[e] = v;
+  v32[e] = (float)v;
+}
+
+__global__ void k_vec_scale(double* x, const double* d, int64_t n,
+                            int divide) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[i] = divide ? x[i] / d[i] : x[i] * d[i];
+}
+
+__global__ void k_grad_vals(const int32_t* row_of, const int32_t* col,
+                            int64_t nnz, const double* lam, const double* x,
+                            double* g) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= nnz) return;
+  g[k] = -lam[row_of[k]] * x[col[k]];
+}
+
+__global__ void k_cast(const double* a, float* b, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+__global__ void k_copy(const double* a, double* b, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+inline unsigned g1(int64_t n) {
+  return (unsigned)ceil_div(n > 0 ? n : 1, 256);
+}
+
+}  // namespace
+
+template <typename T>
+void spmv_plain(const Sell& S, const T* val, const T* x, T* y,
+                hipStream_t st) {
+  hipLaunchKernelGGL((k_spmv<T, EPI_PLAIN>), dim3(spmv_grid(S)),
+                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, S.col, val, x,
+                     (const T*)nullptr, y, (const double*)nullptr,
+                     (double*)nullptr, S.n, S.nslices,
+                     (const double*)nullptr, 0);
+  SGM_CHECK_LAUNCH();
+}
+
+template <typename T>
+void spmv_mpk(const Sell& S, const T* val, const T* x, const T* xprev, T* y,
+              const double* rec, int j, hipStream_t st) {
+  hipLaunchKernelGGL((k_spmv<T, EPI_MPK>), dim3(spmv_grid(S)),
+                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, S.col, val, x,
+                     xprev, y, (const double*)nullptr, (double*)nullptr, S.n,
+                     S.nslices, rec, j);
+  SGM_CHECK_LAUNCH();
+}
+
+int64_t resid_partials(const Sell& S) { return spmv_grid(S); }
+
+int64_t spmv_resid(const Sell& S, const double* val, const double* x,
+                   const double* b, double* r, double* part, hipStream_t st) {
+  hipLaunchKernelGGL((k_spmv<double, EPI_RESID>), dim3(spmv_grid(S)),
+                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, S.col, val, x,
+                     (const double*)nullptr, r, b, part, S.n, S.nslices,
+                     (const double*)nullptr, 0);
+  SGM_CHECK_LAUNCH();
+  return spmv_grid(S);
+}
+
+template void spmv_plain<double>(const Sell&, const double*, const double*,
+                                 double*, hipStream_t);
+template void spmv_plain<float>(const Sell&, const float*, const float*,
+                                float*, hipStream_t);
+template void spmv_mpk<double>(const Sell&, const double*, const double*,
+                               const double*, double*, const double*, int,
+                               hipStream_t);
+template void spmv_mpk<float>(const Sell&, const float*, const float*,
+                              const float*, float*, const double*, int,
+                              hipStream_t);
+
+void reduce_norm(const double* part, int64_t np, double* out,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_norm, dim3(1), dim3(1024), 0, st, part, np,
+                     out);
+  SGM_CHECK_LAUNCH();
+}
+
+template <typename T>
+void scale_into(const double* r, const double* beta, T* q, int64_t n,
+                int64_t ld, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_into<T>, dim3(g1(ld)), dim3(256), 0, st, r,
+                     beta, q, n, ld);
+  SGM_CHECK_LAUNCH();
+}
+template void scale_into<double>(const double*, const double*, double*,
+                                 int64_t, int64_t, hipStream_t);
+template void scale_into<float>(const double*, const double*, float*,
+                                int64_t, int64_t, hipStream_t);
+
+template <typename T>
+void zero_pad_rows(T* Q, int64_t n, int64_t ld, int ncols, hipStream_t st) {
+  if (ld <= n || ncols <= 0) return;
+  hipLaunchKernelGGL(k_zero_pad<T>, dim3(g1((ld - n) * ncols)), dim3(256), 0,
+                     st, Q, n, ld, ncols);
+  SGM_CHECK_LAUNCH();
+}
+template void zero_pad_rows<double>(double*, int64_t, int64_t, int,
+                                    hipStream_t);
+template void zero_pad_rows<float>(float*, int64_t, int64_t, int,
+                                   hipStream_t);
+
+void jacobi_values(const Matrix& M, const Sell& S, double* v64, float* v32,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_jacobi_values, dim3(g1(S.nnz_padded)), dim3(256), 0,
+                     st, S.src, S.col, S.nnz_padded, M.val, M.diag, v64, v32);
+  SGM_CHECK_LAUNCH();
+}
+
+void vec_scale_div(double* x, const double* d, int64_t n, bool divide,
+                   hipStream_t st) {
+  hipLaunchKernelGGL(k_vec_scale, dim3(g1(n)), dim3(256), 0, st, x, d, n,
+                     divide ? 1 : 0);
+  SGM_CHECK_LAUNCH();
+}
+
+void grad_vals(const Matrix& M, const double* lam, const double* x,
+               double* g, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_vals, dim3(g1(M.nnz)), dim3(256), 0, st,
+                     M.row_of, M.col, M.nnz, lam, x, g);
+  SGM_CHECK_LAUNCH();
+}
+
+void cast_f64_f32(const double* a, float* b, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_cast, dim3(g1(n)), dim3(256), 0, st, a, b, n);
+  SGM_CHECK_LAUNCH();
+}
+
+void copy_f64(const double* a, double* b, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy, dim3(g1(n)), dim3(256), 0, st, a, b, n);
+  SGM_CHECK_LAUNCH();
+}
+
+}  // namespace sgm

@@ -1,0 +1,605 @@
+// Tall-skinny block kernels of BCGS2 + CholQR (Alg. 2 / Alg. 4) on CDNA
+// matrix cores: 16x16x4 MFMA in float64 (v_mfma_f64_16x16x4f64) or float32
+// (v_mfma_f32_16x16x4f32, float32 accumulation).
+//
+// MFMA operand layout used throughout (wave64, one 16x16 output tile):
+//   A operand: lane l supplies A[m = l%16][k = l/16]
+//   B operand: lane l supplies B[k = l/16][n = l%16]
+//   result:    lane l holds D[m][n = l%16] in its 4 result registers j with
+//              m = 4(l/16) + j for float32 and m = l/16 + 4j for float64
+//              (checked on gfx950; see drow() below)
+// Every contraction over the long (row) dimension is free to assign rows to
+// (step, k) pairs as long as both operands use the same assignment; the
+// kernels below pick assignments that turn each lane's loads into
+// contiguous vectors of a column-major matrix.
+//
+// Reductions over rows are two-stage and deterministic: per-workgroup
+// partials in a fixed order, then a fixed-order sum over workgroups.  No
+// floating-point atomics, so results are bitwise reproducible.
+#include "internal.h"
+
+namespace sgm {
+
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<double> {
+  typedef d4_t type;
+};
+template <>
+struct Vec4<float> {
+  typedef f4_t type;
+};
+
+template <typename T, int N>
+struct VecN {
+  T v[N];
+};
+
+__device__ __forceinline__ d4_t mfma(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma(float a, float b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Row of the 16x16 result tile held by result register j of lane group
+// g = lane / 16 (the column is lane % 16).
+template <typename T>
+__device__ __forceinline__ int drow(int g, int j) {
+  if constexpr (sizeof(T) == 8) return g + 4 * j;
+  else return 4 * g + j;
+}
+
+template <typename V>
+__device__ __forceinline__ V vzero() {
+  V z;
+  z[0] = 0;
+  z[1] = 0;
+  z[2] = 0;
+  z[3] = 0;
+  return z;
+}
+
+// Load / store MT consecutive elements (MT in {1, 2, 4}); the address is
+// aligned to MT * sizeof(T) by construction (ld and row offsets are
+// multiples of 64 and MT).
+template <typename T, int MT>
+__device__ __forceinline__ void load_rows(const T* p, T (&out)[MT]) {
+  if constexpr (MT == 4) {
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    v4 v = *reinterpret_cast<const v4*>(p);
+    out[0] = v[0]; out[1] = v[1]; out[2] = v[2]; out[3] = v[3];
+  } else if constexpr (MT == 2) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    v2 v = *reinterpret_cast<const v2*>(p);
+    out[0] = v[0]; out[1] = v[1];
+  } else {
+    out[0] = p[0];
+  }
+}
+template <typename T, int MT>
+__device__ __forceinline__ void store_rows(T* p, const T (&in)[MT]) {
+  if constexpr (MT == 4) {
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    v4 v;
+    v[0] = in[0]; v[1] = in[1]; v[2] = in[2]; v[3] = in[3];
+    *reinterpret_cast<v4*>(p) = v;
+  } else if constexpr (MT == 2) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    v2 v;
+    v[0] = in[0]; v[1] = in[1];
+    *reinterpret_cast<v2*>(p) = v;
+  } else {
+    p[0] = in[0];
+  }
+}
+
+constexpr int kBlock = 256;  // 4 wavefronts per workgroup
+
+// ------------------------------------------------------------- A^T B
+// Grid: 1-D, chunks * ntiles workgroups (chunks a multiple of 8).  XCD-aware
+// decode: workgroup id -> (xcd = id % 8, slot = id / 8); the ntiles output
+// tiles of one row chunk get consecutive slots on the same XCD, so they run
+// together and share that XCD's L2 for the A and B rows they all read.
+// Each wavefront consumes 16-row batches; lane (g = l/16, c = l%16) loads
+// rows 4g..4g+3 of one column as a 4-vector, and MFMA step t pairs row
+// 4g + t of A with the same row of B.
+template <typename T, int MT, int NT>
+__global__ __launch_bounds__(kBlock) void k_gemm_tn(
+    const T* __restrict__ A, int64_t lda, int ma, const T* __restrict__ B,
+    int64_t ldb, int nb, const int* __restrict__ ncount, int64_t nbatches,
+    int tiles_n, int ntiles, int chunks, double* __restrict__ part) {
+  typedef typename Vec4<T>::type V;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int g = lane / 16, c16 = lane % 16;
+  const int id = blockIdx.x;
+  const int xcd = id % 8, slot = id / 8;
+  const int tile = slot % ntiles;
+  const int chunk = (slot / ntiles) * 8 + xcd;
+  const int tm = tile / tiles_n, tn = tile % tiles_n;
+  const int m0 = tm * 16 * MT, n0 = tn * 16 * NT;
+  const int nbe = ncount ? min(nb, *ncount) : nb;
+  const int64_t b0 = nbatches * chunk / chunks;
+  const int64_t b1 = nbatches * (chunk + 1) / chunks;
+
+  const T* pa[MT];
+  const T* pb[NT];
+  bool va[MT], vb[NT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i) {
+    const int c = m0 + i * 16 + c16;
+    va[i] = c < ma;
+    pa[i] = A + (int64_t)(va[i] ? c : 0) * lda + 4 * g;
+  }
+#pragma unroll
+  for (int i = 0; i < NT; ++i) {
+    const int c = n0 + i * 16 + c16;
+    vb[i] = c < nbe;
+    pb[i] = B + (int64_t)(vb[i] ? c : 0) * ldb + 4 * g;
+  }
+  V acc[MT][NT];
+#pragma unroll
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[i][j] = vzero<V>();
+
+  for (int64_t bt = b0 + wave; bt < b1; bt += kBlock / kWave) {
+    const int64_t row = bt * 16;
+    V af[MT], bf[NT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+      af[i] = va[i] ? *reinterpret_cast<const V*>(pa[i] + row) : vzero<V>();
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+      bf[j] = vb[j] ? *reinterpret_cast<const V*>(pb[j] + row) : vzero<V>();
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = mfma(af[i][t], bf[j][t], acc[i][j]);
+  }
+
+  // Fixed-order reduction of the 4 wavefronts through LDS.
+  constexpr int NE = MT * NT * 4;
+  __shared__ double red[NE * kWave];
+  for (int w = kBlock / kWave - 1; w >= 1; --w) {
+    if (wave == w) {
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int e = ((i * NT + j) * 4 + q) * kWave + lane;
+            double v = (double)acc[i][j][q];
+            if (w < kBlock / kWave - 1) v += red[e];
+            red[e] = v;
+          }
+    }
+    __syncthreads();
+  }
+  if (wave == 0) {
+    double* out = part + (int64_t)chunk * ma * nb;
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = ((i * NT + j) * 4 + q) * kWave + lane;
+          const int row = m0 + i * 16 + drow<T>(g, q);
+          const int col = n0 + j * 16 + c16;
+          if (row < ma && col < nb)
+            out[(int64_t)col * ma + row] = (double)acc[i][j][q] + red[e];
+        }
+  }
+}
+
+// C(i, j) = sum over chunks of part[c][j * ma + i]; with sym, entries below
+// the diagonal 16x16 tiles are read from the mirrored upper entry.
+__global__ void k_reduce_chunks(const double* __restrict__ part,
+                                int64_t nchunks, int ma, int nb,
+                                double* __restrict__ C, int ldc, int sym) {
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)ma * nb) return;
+  const int i = (int)(e % ma), j = (int)(e / ma);
+  int64_t src = e;
+  if (sym && (i / 16) > (j / 16)) src = (int64_t)i * ma + j;
+  const int64_t stride = (int64_t)ma * nb;
+  double s = 0.0;
+  for (int64_t c = 0; c < nchunks; ++c) s += part[c * stride + src];
+  C[(int64_t)j * ldc + i] = s;
+}
+
+// ------------------------------------------------------------- update / trsm
+// One wavefront owns 16*MT consecutive rows and every column of the block.
+// Tile row m of row-tile t is physical row r0 + MT*m + t, so a lane's A
+// operand for the MT row tiles is one contiguous MT-vector of a column, and
+// the MT results sharing a D index are contiguous rows too.
+// MODE_UPDATE: B(:, 0:nc) = B - A(:, 0:ka) M(0:ka, 0:nc), and (GRAM) the
+//              partial Gram B^T B of the updated rows.
+// MODE_TRSM:   B(:, 0:p) = B(:, 0:p) M(0:p, 0:p) in place, M upper
+//              triangular (tiles below the diagonal are skipped).
+enum { MODE_UPDATE = 0, MODE_TRSM = 1 };
+
+template <typename T, int NT, int MT, int MODE, bool GRAM>
+__global__ __launch_bounds__(kBlock) void k_update(
+    const T* __restrict__ A, int64_t lda, int ka, T* __restrict__ B,
+    int64_t ldb, int nc, const double* __restrict__ M, int ldm,
+    const int* __restrict__ ncount, int64_t nrows, int kc,
+    double* __restrict__ part) {
+  typedef typename Vec4<T>::type V;
+  extern __shared__ char smem_raw[];
+  T* Ms = reinterpret_cast<T*>(smem_raw);
+  constexpr int W16 = NT * 16;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int g = lane / 16, c16 = lane % 16;
+  int nce = nc;
+  if (ncount) nce = min(nc, *ncount);
+  int kae = ka;
+  if (MODE == MODE_TRSM) kae = nce;
+  const int ka4 = (kae + 3) & ~3;
+  const bool single = ka4 <= kc;
+  const int64_t rows_per_wave = 16 * MT;
+  const int64_t rows_per_block = rows_per_wave * (kBlock / kWave);
+  const int64_t nblocks = (nrows + rows_per_block - 1) / rows_per_block;
+
+  auto stage = [&](int k0) {
+    for (int e = threadIdx.x; e < kc * W16; e += kBlock) {
+      const int kk = e / W16, cc = e % W16;
+      const int k = k0 + kk;
+      double v = 0.0;
+      if (k < kae && cc < nce) {
+        v = M[(int64_t)cc * ldm + k];
+        if (MODE == MODE_UPDATE) v = -v;
+      }
+      Ms[e] = (T)v;
+    }
+  };
+
+  constexpr int NG = GRAM ? NT * (NT + 1) / 2 : 1;
+  V gacc[NG];
+#pragma unroll
+  for (int t = 0; t < NG; ++t) gacc[t] = vzero<V>();
+
+  if (single) {
+    stage(0);
+    __syncthreads();
+  }
+  for (int64_t rb = blockIdx.x; rb < nblocks; rb += gridDim.x) {
+    const int64_t r0 = rb * rows_per_block + wave * rows_per_wave;
+    const bool active = r0 < nrows;
+    V acc[MT][NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      const int c = j * 16 + c16;
+      if (MODE == MODE_UPDATE && active && c < nce) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          T v[MT];
+          load_rows<T, MT>(B + (int64_t)c * ldb + r0 + MT * drow<T>(g, q), v);
+#pragma unroll
+          for (int t = 0; t < MT; ++t) acc[t][j][q] = v[t];
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < MT; ++t) acc[t][j] = vzero<V>();
+      }
+    }
+    for (int k0 = 0; k0 < ka4; k0 += kc) {
+      if (!single) {
+        __syncthreads();
+        stage(k0);
+        __syncthreads();
+      }
+      const int kend = min(kc, ka4 - k0);
+      if (active) {
+        for (int kk = 0; kk < kend; kk += 4) {
+          const int k = k0 + kk + g;
+          T a[MT];
+          if (k < kae) {
+            load_rows<T, MT>((MODE == MODE_TRSM ? (const T*)B : A) +
+                                 (int64_t)k * (MODE == MODE_TRSM ? ldb : lda) +
+                                 r0 + MT * c16,
+                             a);
+          } else {
+#pragma unroll
+            for (int t = 0; t < MT; ++t) a[t] = 0;
+          }
+          const T* mrow = Ms + (kk + g) * W16 + c16;
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            if (MODE == MODE_TRSM && (k0 + kk) >= (j + 1) * 16) continue;
+            const T bv = mrow[j * 16];
+#pragma unroll
+            for (int t = 0; t < MT; ++t) acc[t][j] = mfma(a[t], bv, acc[t][j]);
+          }
+        }
+      }
+    }
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        const int c = j * 16 + c16;
+        if (c < nce) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            T v[MT];
+#pragma unroll
+            for (int t = 0; t < MT; ++t) v[t] = acc[t][j][q];
+            store_rows<T, MT>(B + (int64_t)c * ldb + r0 + MT * drow<T>(g, q), v);
+          }
+        }
+      }
+      if constexpr (GRAM) {
+        int tix = 0;
+#pragma unroll
+        for (int j1 = 0; j1 < NT; ++j1)
+#pragma unroll
+          for (int j2 = j1; j2 < NT; ++j2) {
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+#pragma unroll
+              for (int q = 0; q < 4; ++q)
+                gacc[tix] = mfma(acc[t][j1][q], acc[t][j2][q], gacc[tix]);
+            ++tix;
+          }
+      }
+    }
+  }
+  if constexpr (GRAM) {
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(smem_raw);
+    constexpr int NE = NG * 4;
+    for (int w = kBlock / kWave - 1; w >= 1; --w) {
+      if (wave == w) {
+#pragma unroll
+        for (int t = 0; t < NG; ++t)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int e = (t * 4 + q) * kWave + lane;
+            double v = (double)gacc[t][q];
+            if (w < kBlock / kWave - 1) v += red[e];
+            red[e] = v;
+          }
+      }
+      __syncthreads();
+    }
+    if (wave == 0) {
+      double* out = part + (int64_t)blockIdx.x * nc * nc;
+      int tix = 0;
+#pragma unroll
+      for (int j1 = 0; j1 < NT; ++j1)
+#pragma unroll
+        for (int j2 = j1; j2 < NT; ++j2) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int e = (tix * 4 + q) * kWave + lane;
+            const int row = j1 * 16 + drow<T>(g, q);
+            const int col = j2 * 16 + c16;
+            if (row < nc && col < nc)
+              out[(int64_t)col * nc + row] = (double)gacc[tix][q] + red[e];
+          }
+          ++tix;
+        }
+      (void)NE;
+    }
+  }
+}
+
+// x(r) += scale * sum_j Q(r, j) y(j), j < k (float64 accumulation).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv_update(
+    const T* __restrict__ Q, int64_t ldq, const double* __restrict__ y,
+    const int* __restrict__ kdev, int kmax, const double* __restrict__ sdev,
+    double* __restrict__ x, int64_t n) {
+  __shared__ double ys[1024];
+  const int k = kdev ? min(kmax, *kdev) : kmax;
+  const double sc = sdev ? sdev[0] : 1.0;
+  for (int base = 0; base < k; base += 1024) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < 1024 && base + j < k; j += blockDim.x)
+      ys[j] = y[base + j];
+    __syncthreads();
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
+         r += (int64_t)gridDim.x * blockDim.x) {
+      double acc = 0.0;
+      const int kk = min(1024, k - base);
+      const T* q = Q + (int64_t)base * ldq + r;
+      int j = 0;
+      for (; j + 4 <= kk; j += 4) {
+        acc += (double)q[(int64_t)j * ldq] * ys[j];
+        acc += (double)q[(int64_t)(j + 1) * ldq] * ys[j + 1];
+        acc += (double)q[(int64_t)(j + 2) * ldq] * ys[j + 2];
+        acc += (double)q[(int64_t)(j + 3) * ldq] * ys[j + 3];
+      }
+      for (; j < kk; ++j) acc += (double)q[(int64_t)j * ldq] * ys[j];
+      x[r] += sc * acc;
+    }
+  }
+}
+
+// ------------------------------------------------------------- dispatch
+int pick_chunks(int ntiles, int64_t nbatches, int64_t per_chunk,
+                const Partials& P) {
+  int64_t target = (1024 + ntiles - 1) / ntiles;
+  int64_t maxc = nbatches / 4;  // at least one batch per wavefront
+  if (target > maxc) target = maxc;
+  int64_t capc = per_chunk > 0 ? P.cap / per_chunk : target;
+  if (target > capc) target = capc;
+  target = target / 8 * 8;
+  if (target < 8) target = 8;
+  if (target * per_chunk > P.cap)
+    throw Error{SGM_EINVAL, "partial-sum scratch too small for this block"};
+  return (int)target;
+}
+
+template <typename T, int MT, int NT>
+void launch_gemm_tn(const T* A, int64_t lda, int ma, const T* B, int64_t ldb,
+                    int nb, const int* ncount, int64_t nbatches, int tiles_n,
+                    int ntiles, int chunks, double* part, hipStream_t st) {
+  hipLaunchKernelGGL((k_gemm_tn<T, MT, NT>), dim3(chunks * ntiles),
+                     dim3(kBlock), 0, st, A, lda, ma, B, ldb, nb, ncount,
+                     nbatches, tiles_n, ntiles, chunks, part);
+  SGM_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+template <typename T>
+void gemm_tn(const T* A, int64_t lda, int ma, const T* B, int64_t ldb,
+             int nb, const int* ncount, int64_t nrows, double* C, int ldc,
+             Partials& P, hipStream_t st) {
+  if (ma <= 0 || nb <= 0) return;
+  const int mt_all = (ma + 15) / 16, nt_all = (nb + 15) / 16;
+  int NT = nt_all <= 1 ? 1 : (nt_all <= 2 ? 2 : 4);
+  const int mt_cap = sizeof(T) == 8 ? (NT == 4 ? 2 : 4) : (NT == 4 ? 4 : 8);
+  int MT = 1;
+  while (MT < mt_all && MT < mt_cap) MT *= 2;
+  const int tiles_n = (nt_all + NT - 1) / NT;
+  const int tiles_m = (mt_all + MT - 1) / MT;
+  const int ntiles = tiles_m * tiles_n;
+  const int64_t nbatches = (nrows + 15) / 16;
+  const int chunks =
+      pick_chunks(ntiles, nbatches, (int64_t)ma * nb, P);
+#define SGM_GT(mt, nt)                                                      \
+  if (MT == mt && NT == nt) {                                               \
+    launch_gemm_tn<T, mt, nt>(A, lda, ma, B, ldb, nb, ncount, nbatches,     \
+                              tiles_n, ntiles, chunks, P.buf, st);          \
+  } else
+  SGM_GT(1, 1) SGM_GT(2, 1) SGM_GT(4, 1) SGM_GT(8, 1)
+  SGM_GT(1, 2) SGM_GT(2, 2) SGM_GT(4, 2) SGM_GT(8, 2)
+  SGM_GT(1, 4) SGM_GT(2, 4) SGM_GT(4, 4)
+  { throw Error{SGM_EINVAL, "gemm_tn: no kernel for this shape"}; }
+#undef SGM_GT
+  const int64_t ne = (int64_t)ma * nb;
+  hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)ceil_div(ne, 256)),
+                     dim3(256), 0, st, P.buf, (int64_t)chunks, ma, nb, C, ldc,
+                     0);
+  SGM_CHECK_LAUNCH();
+}
+
+namespace {
+
+constexpr int kLdsBudget = 64 * 1024;
+
+template <typename T, int NT, int MT, int MODE, bool GRAM>
+void launch_update(const T* A, int64_t lda, int ka, T* B, int64_t ldb,
+                   int nc, const double* M, int ldm, const int* ncount,
+                   int64_t nrows, double* G, int ldg, Partials& P,
+                   hipStream_t st) {
+  const int W16 = NT * 16;
+  const int ka4 = (ka + 3) & ~3;
+  int kc = kLdsBudget / (W16 * (int)sizeof(T));
+  kc &= ~3;
+  if (kc > ka4) kc = ka4 < 4 ? 4 : ka4;
+  size_t lds = (size_t)kc * W16 * sizeof(T);
+  if (GRAM) {
+    const size_t red = (size_t)(NT * (NT + 1) / 2) * 4 * kWave * sizeof(double);
+    if (red > lds) lds = red;
+  }
+  const int64_t rows_per_block = 16 * MT * (kBlock / kWave);
+  const int64_t nblocks = ceil_div(nrows, rows_per_block);
+  int64_t grid = nblocks < 1024 ? nblocks : 1024;
+  if (grid < 1) grid = 1;
+  if (GRAM && grid * nc * nc > P.cap) {
+    grid = P.cap / ((int64_t)nc * nc);
+    if (grid < 1) throw Error{SGM_EINVAL, "partial scratch too small"};
+  }
+  hipLaunchKernelGGL((k_update<T, NT, MT, MODE, GRAM>), dim3((unsigned)grid),
+                     dim3(kBlock), lds, st, A, lda, ka, B, ldb, nc, M, ldm,
+                     ncount, nrows, kc, GRAM ? P.buf : (double*)nullptr);
+  SGM_CHECK_LAUNCH();
+  if (GRAM) {
+    const int64_t ne = (int64_t)nc * nc;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)ceil_div(ne, 256)),
+                       dim3(256), 0, st, P.buf, grid, nc, nc, G, ldg, 1);
+    SGM_CHECK_LAUNCH();
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void update_gram(const T* A, int64_t lda, int ka, T* B, int64_t ldb, int nc,
+                 const double* M, int ldm, const int* ncount, int64_t nrows,
+                 double* G, int ldg, Partials& P, hipStream_t st) {
+  if (nc <= 0) return;
+  const int nt = (nc + 15) / 16;
+  const bool fuse = G != nullptr && nt <= 4;
+#define SGM_UP(NTv, MTv)                                                      \
+  if (nt == NTv) {                                                            \
+    if (fuse)                                                                 \
+      launch_update<T, NTv, MTv, MODE_UPDATE, (NTv <= 4)>(                    \
+          A, lda, ka, B, ldb, nc, M, ldm, ncount, nrows, G, ldg, P, st);      \
+    else                                                                      \
+      launch_update<T, NTv, MTv, MODE_UPDATE, false>(                         \
+          A, lda, ka, B, ldb, nc, M, ldm, ncount, nrows, nullptr, 0, P, st);  \
+  } else
+  SGM_UP(1, 4) SGM_UP(2, 4) SGM_UP(3, 2) SGM_UP(4, 2) SGM_UP(5, 1)
+  SGM_UP(6, 1) SGM_UP(7, 1) SGM_UP(8, 1) SGM_UP(9, 1) SGM_UP(10, 1)
+  SGM_UP(11, 1) SGM_UP(12, 1) SGM_UP(13, 1) SGM_UP(14, 1) SGM_UP(15, 1)
+  SGM_UP(16, 1)
+  { throw Error{SGM_EINVAL, "update: block wider than 256 columns"}; }
+#undef SGM_UP
+  if (G != nullptr && !fuse)
+    gemm_tn<T>(B, ldb, nc, B, ldb, nc, ncount, nrows, G, ldg, P, st);
+}
+
+template <typename T>
+void trsm_inv(T* B, int64_t ldb, int s, const double* Rinv, int ldr,
+              const int* pcount, int64_t nrows, hipStream_t st) {
+  if (s <= 0) return;
+  Partials none;
+  const int nt = (s + 15) / 16;
+#define SGM_TR(NTv, MTv)                                                      \
+  if (nt == NTv) {                                                            \
+    launch_update<T, NTv, MTv, MODE_TRSM, false>(                             \
+        nullptr, 0, s, B, ldb, s, Rinv, ldr, pcount, nrows, nullptr, 0, none, \
+        st);                                                                  \
+  } else
+  SGM_TR(1, 4) SGM_TR(2, 4) SGM_TR(3, 2) SGM_TR(4, 2) SGM_TR(5, 1)
+  SGM_TR(6, 1) SGM_TR(7, 1) SGM_TR(8, 1) SGM_TR(9, 1) SGM_TR(10, 1)
+  SGM_TR(11, 1) SGM_TR(12, 1) SGM_TR(13, 1) SGM_TR(14, 1) SGM_TR(15, 1)
+  SGM_TR(16, 1)
+  { throw Error{SGM_EINVAL, "trsm: block wider than 256 columns"}; }
+#undef SGM_TR
+}
+
+template <typename T>
+void gemv_update(const T* Q, int64_t ldq, const double* y, const int* kdev,
+                 int kmax, const double* sdev, double* x, int64_t n,
+                 hipStream_t st) {
+  int64_t grid = ceil_div(n, 256);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_gemv_update<T>, dim3((unsigned)grid), dim3(256), 0,
+                     st, Q, ldq, y, kdev, kmax, sdev, x, n);
+  SGM_CHECK_LAUNCH();
+}
+
+#define SGM_INST(T)                                                          \
+  template void gemm_tn<T>(const T*, int64_t, int, const T*, int64_t, int,   \
+                           const int*, int64_t, double*, int, Partials&,     \
+                           hipStream_t);                                     \
+  template void update_gram<T>(const T*, int64_t, int, T*, int64_t, int,     \
+                               const double*, int, const int*, int64_t,      \
+                               double*, int, Partials&, hipStream_t);        \
+  template void trsm_inv<T>(T*, int64_t, int, const double*, int,            \
+                            const int*, int64_t, hipStream_t);               \
+  template void gemv_update<T>(const T*, int64_t, const double*, const int*, \
+                               int, const double*, double*, int64_t,         \
+                               hipStream_t);
+SGM_INST(double)
+SGM_INST(float)
+#undef SGM_INST
+
+}  // namespace sgm

@@ -1,0 +1,373 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on
+the same seeded inputs.  Step-level checks (SpMV, matrix powers kernel,
+BCGS2 + partial CholQR2, shifts) and end-to-end solves at sizes the oracle
+finishes in seconds, spanning several tiles, wavefront slices and a ragged
+tail (n not a multiple of 64).
+
+Tolerances: float64 steps agree to a few ulps times the condition of the
+step; solves agree to relative solution difference <= 1e-8 and iteration
+counts within +-s_max of the oracle; integer decisions (accepted block
+sizes, Leja order, s0*) are compared exactly where both sides take them in
+float64 away from a threshold.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads as W
+from oracle import sstep_gmres as o
+
+pytestmark = pytest.mark.gpu
+
+
+def csr(A):
+    return o.csr_matrix(A.n, A.row_ptr, A.col, A.val)
+
+
+def flat_cols(torch, M, ld):
+    """Column-major (ld x k) flat device tensor from an n x k array."""
+    n, k = M.shape
+    buf = np.zeros((k, ld), dtype=M.dtype)
+    buf[:, :n] = M.T
+    return torch.tensor(buf.ravel(), device="cuda")
+
+
+def cols_of(t, n, ld, k):
+    return t.cpu().numpy().reshape(k, ld)[:, :n].T
+
+
+# ------------------------------------------------------------------ SpMV
+
+@pytest.mark.parametrize("mk", [lambda: W.conv_diff_2d(64, 10.0),
+                                lambda: W.poisson_3d(23),
+                                lambda: W.banded_problem(3001, band=300)[0]])
+def test_spmv_matches_csr_product(lib, mk):
+    import torch
+    A = mk()
+    M = csr(A)
+    G = lib.Matrix.from_csr(A)
+    x = np.random.default_rng(0).standard_normal(A.n)
+    y = G.spmv(x).cpu().numpy()
+    yr = M @ x
+    scale = np.abs(M) @ np.abs(x)
+    assert np.all(np.abs(y - yr) <= 4 * 2.0 ** -52 * 8 * scale + 1e-300)
+    yt = G.spmv(x, transpose=True).cpu().numpy()
+    assert np.all(np.abs(yt - M.T @ x) <= 4 * 2.0 ** -52 * 8 *
+                  (np.abs(M.T) @ np.abs(x)) + 1e-300)
+    x32 = x.astype(np.float32)
+    y32 = G.spmv(torch.tensor(x32, device="cuda"),
+                 precision="fp32_ir").cpu().numpy()
+    yr32 = M.astype(np.float32) @ x32
+    assert np.all(np.abs(y32 - yr32) <= 4 * 2.0 ** -23 * 8 * scale + 1e-30)
+    info = G.info()
+    assert info["n"] == A.n and info["nnz"] == A.nnz
+    assert info["sell_nnz"] >= A.nnz
+
+
+# ------------------------------------------------------------------ MPK
+
+def test_mpk_scaled_newton_with_complex_pair(lib):
+    import torch
+    A = W.conv_diff_2d(40, 10.0)
+    M = csr(A)
+    n, ld, s = A.n, ((A.n + 63) // 64) * 64, 9
+    rng = np.random.default_rng(1)
+    q = rng.standard_normal(n)
+    q /= np.linalg.norm(q)
+    ritz = np.array([7.5, 2.0 + 1.0j, 2.0 - 1.0j, 0.5, 5.0, 3.0 + 0.25j,
+                     3.0 - 0.25j, 1.0, 6.0])
+    sh = o.newton_shifts(o.leja_order(ritz), scaled=True)
+    eng = o._Engine(M, o.Options())
+    V = eng.mpk(q, sh, s)
+    rec = np.stack([sh.theta, sh.gamma, sh.delta], 1)
+    Q0 = np.zeros((n, s + 1))
+    Q0[:, 0] = q
+    Qd = flat_cols(torch, Q0, ld)
+    lib.mpk(lib.Matrix.from_csr(A), Qd, ld, 0, s, rec)
+    Vg = cols_of(Qd, n, ld, s + 1)[:, 1:]
+    for j in range(s):
+        err = np.linalg.norm(Vg[:, j] - V[:, j]) / np.linalg.norm(V[:, j])
+        assert err <= 1e-13 * (j + 1), (j, err)
+
+
+# ------------------------------------------------------------------ block QR
+
+def _basis_and_block(A, i, s, seed=2, basis="scaled_newton"):
+    """An orthonormal Q(:, 0:i) from the oracle and the next MPK block."""
+    M = csr(A)
+    b = W.rhs(A.n, seed)
+    r = o.solve(M, b, opts=o.Options(s_max=8, restart=i - 1, max_restarts=0,
+                                     tol=1e-300, record=True, basis=basis))
+    Q = r.trace["Q_first_cycle"][:, :i]
+    sh = r.shifts
+    eng = o._Engine(M, o.Options())
+    V = eng.mpk(Q[:, i - 1], sh, s)
+    return M, Q, V
+
+
+@pytest.mark.parametrize("i,s", [(1, 8), (9, 8), (33, 16), (70, 32),
+                                 (97, 32)])
+def test_block_orth_matches_oracle(lib, i, s):
+    import torch
+    A = W.conv_diff_2d(64, 10.0)
+    M, Qi, V = _basis_and_block(A, i, s)
+    n, ld = A.n, ((A.n + 63) // 64) * 64
+    ref = o.block_orth(np.asfortranarray(Qi.copy()), i, V.copy(),
+                       o.default_omega(o.U64))
+    Qd = flat_cols(torch, np.concatenate([Qi, V], 1), ld)
+    p, Rt, Rk = lib.block_orth(Qd, n, ld, i, s)
+    assert p == ref.p
+    Qg = cols_of(Qd, n, ld, i + s)
+    Qk = Qg[:, i:i + p]
+    assert np.abs(Qk - ref.Qk).max() <= 1e-9
+    assert np.abs(Rt[:, :p] - ref.R_top).max() <= 1e-9 * max(1, np.abs(ref.R_top).max())
+    assert np.abs(np.triu(Rk[:p, :p]) - ref.R_kk).max() <= 1e-9 * np.abs(ref.R_kk).max()
+    # orthogonality of the whole basis (P4)
+    assert o.loo(Qg[:, :i + p]) <= 1e-12
+
+
+def test_block_orth_truncates_monomial(lib):
+    """Monomial basis on the Test 1 diagonal matrix: partial CholQR accepts
+    6 of 10 vectors (Sec. 4.1), as the oracle does."""
+    import torch
+    A = W.diagonal(np.linspace(0.1, 10.0, 10000))
+    n, ld = A.n, ((A.n + 63) // 64) * 64
+    q = np.ones(n) / math.sqrt(n)
+    V = np.empty((n, 10))
+    v = q
+    for j in range(10):
+        v = A.val * v
+        V[:, j] = v
+    ref = o.block_orth(q[:, None].copy(), 1, V.copy(), 1e7)
+    Qd = flat_cols(torch, np.concatenate([q[:, None], V], 1), ld)
+    p, Rt, Rk = lib.block_orth(Qd, n, ld, 1, 10, omega=1e7)
+    assert p == ref.p == 6
+
+
+# ------------------------------------------------------------------ shifts
+
+def test_shifts_match_oracle_on_arnoldi_hessenberg(lib):
+    A = W.conv_diff_2d(64, 10.0)
+    M = csr(A)
+    r = o.solve(M, W.rhs(A.n, 1), opts=o.Options(
+        s_max=1, restart=24, max_restarts=0, tol=1e-300, basis="monomial",
+        record=True))
+    H = r.trace["H_first_cycle"][:24, :24].copy()
+    ritz, rec, s0, hits = lib.shifts(H, 24, omega_est=o.default_omega(o.U64))
+    ev = np.linalg.eigvals(H)
+    lo = o.leja_order(ev)
+    sh = o.newton_shifts(lo, scaled=True)
+    s0r, _ = o.estimator(sh.ritz, sh.gamma, o.U64, o.default_omega(o.U64))
+    scale = np.abs(H).max()
+    assert np.abs(np.sort_complex(ritz) - np.sort_complex(ev)).max() <= 1e-10 * scale
+    assert np.abs(ritz - lo).max() <= 1e-9 * scale   # same Leja order
+    assert np.allclose(rec[:, 0], sh.theta, atol=1e-9 * scale)
+    assert np.allclose(rec[:, 1], sh.gamma, rtol=1e-8)
+    assert np.allclose(rec[:, 2], sh.delta, atol=1e-8 * scale)
+    assert s0 == s0r
+
+
+@pytest.mark.parametrize("lmax,expect", [(200.0, 134), (2000.0, 17)])
+def test_estimator_on_gpu_matches_oracle_and_paper(lib, lmax, expect):
+    """Sec. 4.4 Test 8 through the GPU path (Francis QR on a 200 x 200
+    Hessenberg held in global memory, Leja, estimator): same s0* as the
+    oracle, within +-3 of the paper's value."""
+    lam = np.arange(1.0, 201.0)
+    lam[-1] = lmax
+    Ad = sp.diags(lam).tocsr()
+    v = np.random.default_rng(11).standard_normal(200)
+    r = o.solve(Ad, v, opts=o.Options(s_max=1, restart=200, max_restarts=0,
+                                      tol=1e-300, basis="monomial",
+                                      record=True))
+    H = r.trace["H_first_cycle"][:200, :200].copy()
+    ritz, rec, s0, hits = lib.shifts(H, 200, omega_est=1e7)
+    sh = o.newton_shifts(o.leja_order(np.linalg.eigvals(H)), scaled=True)
+    s0r, _ = o.estimator(sh.ritz, sh.gamma, o.U64, 1e7)
+    assert abs(s0 - s0r) <= 1
+    assert abs(s0 - expect) <= 3
+    assert np.abs(np.sort(ritz.real) - lam).max() <= 1e-8 * lmax
+
+
+# ------------------------------------------------------------------ solves
+
+def _compare_solve(lib, A, b, s_max, restart, tol, x0=None, **kw):
+    opts = dict(s_max=s_max, restart=restart, tol=tol)
+    opts.update(kw)
+    okw = {k: v for k, v in opts.items() if k not in ("precision", "transpose")}
+    M = csr(A)
+    if opts.get("transpose"):
+        M = M.T.tocsr()
+    ref = o.solve(M, b, x0, o.Options(max_restarts=400, **okw))
+    G = lib.Matrix.from_csr(A)
+    gpu = lib.solve(G, b, x0=x0, max_restarts=400, **opts)
+    x = gpu.x.cpu().numpy()
+    assert gpu.status == lib.OK
+    assert ref.status == "ok"
+    assert abs(gpu.info["iters"] - ref.iters) <= s_max, (gpu.info["iters"], ref.iters)
+    rel = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    true = np.linalg.norm(b - M @ x) / np.linalg.norm(b - M @ (x0 if x0 is not None else 0 * b))
+    assert true <= tol * 1.0001
+    return gpu, ref, rel
+
+
+def test_solve_convdiff_64_parity(lib):
+    """cfg: 2D convection-diffusion 64^2, scaled Newton s_max 8, restart 64,
+    tol 1e-10 (the smallest bench workload)."""
+    A = W.conv_diff_2d(64, 10.0)
+    b = W.rhs(A.n, 1)
+    gpu, ref, rel = _compare_solve(lib, A, b, 8, 64, 1e-10)
+    assert rel <= 1e-8
+    assert gpu.info["s0_est"] == ref.s0_est
+    # identical adaptive block sizes and residual estimates to rounding
+    assert list(gpu.s_hist) == ref.s_hist
+    h, hr = np.array(gpu.res_hist), np.array(ref.res_hist)
+    assert h.size == hr.size
+    assert np.all(np.abs(h - hr) <= 1e-6 * hr + 1e-13)
+
+
+@pytest.mark.parametrize("basis", ["monomial", "newton"])
+def test_solve_other_bases(lib, basis):
+    A = W.conv_diff_2d(32, 10.0)
+    b = W.rhs(A.n, 2)
+    gpu, ref, rel = _compare_solve(lib, A, b, 6, 48, 1e-10, basis=basis)
+    assert rel <= 1e-8
+    assert list(gpu.s_hist) == ref.s_hist
+
+
+def test_solve_ragged_poisson_restarts_x0(lib):
+    """n = 27^3 (not a multiple of 64), restarts, nonzero x0."""
+    A = W.poisson_3d(27)
+    b = W.rhs(A.n, 3)
+    x0 = np.random.default_rng(4).standard_normal(A.n) * 0.01
+    gpu, ref, rel = _compare_solve(lib, A, b, 16, 48, 1e-10, x0=x0)
+    assert rel <= 1e-8
+    assert gpu.info["restarts"] >= 1
+
+
+def test_solve_no_ritz_reuse_and_no_estimator(lib):
+    A = W.conv_diff_2d(32, 10.0)
+    b = W.rhs(A.n, 5)
+    gpu, ref, rel = _compare_solve(lib, A, b, 8, 40, 1e-10, ritz_reuse=False,
+                                   use_estimator=False)
+    assert rel <= 1e-8
+
+
+def test_solve_user_shifts_single_block(lib):
+    """Test 3 (Sec. 4.2) shape: diagonal matrix, exact spectrum as shifts,
+    one block of s = 60 accepted."""
+    lam = np.linspace(0.1, 10.0, 5000)
+    A = W.diagonal(lam)
+    b = np.ones(A.n)
+    ritz = np.linspace(0.1, 10.0, 60) + 1e-3
+    gpu, ref, rel = _compare_solve(lib, A, b, 60, 60, 1e-12, shifts=ritz,
+                                   use_estimator=False)
+    assert gpu.s_hist[0] == ref.s_hist[0]
+
+
+def test_solve_jacobi_variable_coefficients(lib):
+    """cfg shape: 3D variable-coefficient convection-diffusion with right
+    Jacobi (column-scaling) preconditioning, at 14^3."""
+    A = W.var_conv_diff_3d(14, seed=3)
+    b = W.rhs(A.n, 3)
+    gpu, ref, rel = _compare_solve(lib, A, b, 16, 64, 1e-10, precond="jacobi")
+    assert rel <= 1e-8
+
+
+def test_solve_transpose(lib):
+    A = W.conv_diff_2d(32, 10.0)
+    b = W.rhs(A.n, 6)
+    gpu, ref, rel = _compare_solve(lib, A, b, 8, 64, 1e-10, transpose=True)
+    assert rel <= 1e-8
+
+
+def test_fp32_inner_refinement(lib):
+    """Float32 inner cycles inside float64 refinement reach the float64
+    tolerance; the answer matches the float64 oracle to 1e-8."""
+    A = W.conv_diff_2d(48, 10.0)
+    b = W.rhs(A.n, 7)
+    M = csr(A)
+    ref = o.solve(M, b, opts=o.Options(s_max=8, restart=64, tol=1e-10))
+    G = lib.Matrix.from_csr(A)
+    r = lib.solve(G, b, s_max=8, restart=64, tol=1e-10, precision="fp32_ir",
+                  inner_tol=1e-6)
+    x = r.x.cpu().numpy()
+    assert r.status == lib.OK
+    assert np.linalg.norm(b - M @ x) / np.linalg.norm(b) <= 1e-10
+    assert np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x) <= 1e-8
+    ir = o.solve_ir(M, b, opts=o.Options(s_max=8, restart=64, tol=1e-10),
+                    inner_tol=1e-6)
+    assert abs(r.info["outer_iters"] - ir.outer) <= 1
+
+
+def test_happy_breakdown(lib):
+    lam = np.arange(1.0, 101.0)
+    A = W.diagonal(lam)
+    b = np.zeros(100)
+    b[7] = 3.0
+    G = lib.Matrix.from_csr(A)
+    r = lib.solve(G, b, s_max=4, restart=20, tol=1e-14)
+    assert r.status == lib.OK and r.info["iters"] == 1
+    assert np.allclose(r.x.cpu().numpy(), b / lam, rtol=1e-15, atol=0)
+
+
+def test_invalid_csr_rejected(lib):
+    rp = np.array([0, 1, 2], dtype=np.int32)
+    col = np.array([0, 5], dtype=np.int32)  # column out of range
+    with pytest.raises(lib.SgmError):
+        lib.Matrix(2, rp, col, np.ones(2))
+
+
+def test_deterministic_bitwise(lib):
+    """Two runs give bit-identical iterates: every reduction is in a fixed
+    order (no floating-point atomics)."""
+    A = W.poisson_3d(20)
+    b = W.rhs(A.n, 8)
+    G = lib.Matrix.from_csr(A)
+    x1 = lib.solve(G, b, s_max=16, restart=64, tol=1e-10).x.cpu().numpy()
+    x2 = lib.solve(G, b, s_max=16, restart=64, tol=1e-10).x.cpu().numpy()
+    assert np.array_equal(x1, x2)
+
+
+# ------------------------------------------------------------------ adjoint
+
+def test_autograd_adjoint_n4096(lib):
+    """Gradients of L = 0.5 ||x - x*||^2 w.r.t. b and the CSR values through
+    the differentiable solve: against the dense reference gradient and
+    central differences along random directions (1e-6 relative)."""
+    import torch
+    n = 4096
+    A, b, xs = W.banded_problem(n, seed=4, band=1000)
+    G = lib.Matrix.from_csr(A)
+    opts = dict(s_max=32, restart=128, tol=1e-13, max_restarts=50)
+    vals = torch.tensor(A.val, device="cuda", requires_grad=True)
+    bt = torch.tensor(b, device="cuda", requires_grad=True)
+    xst = torch.tensor(xs, device="cuda")
+    x = lib.sstep_solve(vals, bt, G, **opts)
+    loss = 0.5 * ((x - xst) ** 2).sum()
+    loss.backward()
+    gv = vals.grad.cpu().numpy()
+    gb = bt.grad.cpu().numpy()
+    Ad = A.to_dense()
+    xd = np.linalg.solve(Ad, b)
+    lamd = np.linalg.solve(Ad.T, xd - xs)
+    rows = np.repeat(np.arange(n), np.diff(A.row_ptr))
+    gvd = -lamd[rows] * xd[A.col]
+    assert np.linalg.norm(gb - lamd) <= 1e-10 * np.linalg.norm(lamd)
+    assert np.linalg.norm(gv - gvd) <= 1e-10 * np.linalg.norm(gvd)
+
+    def L(v, bb):
+        with torch.no_grad():
+            G.update_values(torch.tensor(v, device="cuda"))
+            xx = lib.solve(G, bb, **opts).x.cpu().numpy()
+        return 0.5 * float(np.sum((xx - xs) ** 2))
+
+    rng = np.random.default_rng(9)
+    h = 1e-6
+    dv = rng.standard_normal(A.nnz) * np.abs(A.val)
+    fd = (L(A.val + h * dv, b) - L(A.val - h * dv, b)) / (2 * h)
+    assert abs(fd - gv @ dv) <= 1e-6 * abs(fd)
+    db = rng.standard_normal(n)
+    fd = (L(A.val, b + h * db) - L(A.val, b - h * db)) / (2 * h)
+    assert abs(fd - gb @ db) <= 1e-6 * abs(fd)
