@@ -1,0 +1,226 @@
+"""Benchmark: time to relative residual 1e-10 of adaptive s-step GMRES on
+one MI355X, float64 and float32-inner / float64-refinement, on the 3D
+Poisson workload (7-point, 128^3 interior grid, n = 2,097,152,
+nnz = 14,581,760, b ~ N(0,1) seed 2, x0 = 0, scaled Newton basis,
+s_max = 32, restart 128).
+
+One step = one float64 solve plus one float32-IR solve of that system to
+||b - A x|| / ||b|| <= 1e-10, with the matrix analysed and every input
+already resident in HBM.  Prints ONE JSON line (see keys below).
+
+Roofline: the dominant kernel is the SELL SpMV of the matrix powers kernel
+(float64).  Its average launch duration comes from the HIP event pair the
+library records around every MPK launch on the solve's stream, during the
+timed steps; algorithmic bytes per launch are
+nnz (8 + 4) + 4 (n + 1) + 2 * 8 n (values + column indices, row pointers,
+x read once, y written once).  `traffic` comes from a committed rocprofv3
+FETCH_SIZE / WRITE_SIZE summary under profiles/, when it was taken on the
+current SpMV source (matching hash), else null.
+
+CPU baseline: the oracle (numpy/scipy, float64) timed on the host on a
+bounded sample -- one full restart cycle (128 iterations) of the same solve
+-- and scaled to the float64 solve's iteration count.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("time to rel-res 1e-10 (FP64 vs FP32-IR); SpMV/basis HBM GB/s")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmv_source_hash():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2303_08953_amd", "csrc",
+                           "spmv.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_hash):
+    p = os.path.join(ROOT, "profiles", "spmv_poisson3d_128_traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("spmv_source_sha256_16") != kernel_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(A, b, gpu_iters, restart, s_max):
+    """The oracle, as it stands, on one restart cycle of the same solve."""
+    import numpy as np
+    from oracle import sstep_gmres as o
+    try:
+        from threadpoolctl import threadpool_info
+        thr = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:
+        thr = 1
+    M = o.csr_matrix(A.n, A.row_ptr, A.col, A.val)
+    t0 = time.perf_counter()
+    r = o.solve(M, b, opts=o.Options(s_max=s_max, restart=restart,
+                                     tol=1e-10, max_restarts=0))
+    dt = time.perf_counter() - t0
+    its = max(1, r.iters)
+    est_ms = dt * 1e3 * gpu_iters / its
+    return {"value": round(est_ms, 1), "unit": "ms", "cores": int(thr),
+            "kind": "oracle",
+            "sample": (f"one restart cycle ({its} iterations, {dt:.1f} s) of "
+                       f"the float64 solve on the same system, scaled to the "
+                       f"GPU solve's {gpu_iters} iterations")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nx", type=int, default=128)
+    ap.add_argument("--mode", choices=["both", "fp64", "fp32_ir"],
+                    default="both")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="run one plain device copy of this size (for the "
+                         "rocprof counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on exactly one GPU; --gpus "
+              f"{args.gpus} is not supported (the multi-GPU design is "
+              "described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2303_08953_amd as sgm
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    s_max, restart, tol = 32, 128, 1e-10
+    log(f"[bench] building poisson3d_{args.nx}")
+    A = W.poisson_3d(args.nx)
+    b_host = W.rhs(A.n, 2)
+    G = sgm.Matrix.from_csr(A)
+    b = torch.tensor(b_host, device="cuda")
+    x = torch.empty_like(b)
+    ws = sgm.Workspace()
+    o64 = dict(s_max=s_max, restart=restart, tol=tol, max_restarts=1000)
+    o32 = dict(o64, precision="fp32_ir", inner_tol=1e-6, max_outer=500)
+    modes = {"both": [("fp64", o64), ("fp32_ir", o32)],
+             "fp64": [("fp64", o64)], "fp32_ir": [("fp32_ir", o32)]}[args.mode]
+
+    if args.calibrate_copy_mb > 0:
+        nel = args.calibrate_copy_mb * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy of {args.calibrate_copy_mb} MiB done")
+
+    def run(opts):
+        t0 = time.perf_counter()
+        r = sgm.solve(G, b, out=x, workspace=ws, **opts)
+        torch.cuda.synchronize()
+        return r, (time.perf_counter() - t0) * 1e3
+
+    for w in range(args.warmup):
+        for name, opts in modes:
+            r, ms = run(opts)
+            log(f"[bench] warmup {w} {name}: {ms:.1f} ms iters "
+                f"{r.info['iters']} rel {r.info['rel_res_true']:.2e}")
+
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    per = {name: [] for name, _ in modes}
+    infos = {}
+    for k in range(args.steps):
+        for name, opts in modes:
+            r, ms = run(opts)
+            per[name].append(ms)
+            infos.setdefault(name, []).append(r)
+            log(f"[bench] step {k} {name}: {ms:.1f} ms iters "
+                f"{r.info['iters']} rel {r.info['rel_res_true']:.2e}")
+    torch.cuda.synchronize()
+    total_ms = (time.perf_counter() - t_start) * 1e3
+
+    def summary(name):
+        rs = infos[name]
+        last = rs[-1]
+        i = last.info
+        ok = all(rr.status == sgm.OK and rr.info["rel_res_true"] <= tol
+                 for rr in rs)
+        return {"ms": round(float(np.mean(per[name])), 3),
+                "ms_min": round(float(np.min(per[name])), 3),
+                "converged": bool(ok), "iters": i["iters"],
+                "restarts": i["restarts"], "outer_iters": i["outer_iters"],
+                "rel_res_true": i["rel_res_true"], "s0_est": i["s0_est"],
+                "s_init": i["s_init"],
+                "blocks": int(len(last.s_hist)),
+                "s_hist_head": [int(v) for v in last.s_hist[:40]],
+                "phase_ms": {"setup": round(i["t_phase_ms"][0], 3),
+                             "prephase_shifts": round(i["t_phase_ms"][1], 3),
+                             "mpk": round(i["t_phase_ms"][2], 3),
+                             "orth": round(i["t_phase_ms"][3], 3),
+                             "hess_givens": round(i["t_phase_ms"][4], 3),
+                             "cycle_end": round(i["t_phase_ms"][5], 3),
+                             "total": round(i["t_phase_ms"][7], 3)}}
+
+    out = {"metric": METRIC, "unit": "ms", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(total_ms / max(1, args.steps), 3),
+           "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic"}
+    primary = "fp64" if "fp64" in per else "fp32_ir"
+    out["value"] = round(float(np.mean(per[primary])), 3)
+    out["dtype"] = "f64" if primary == "fp64" else "f32/f64"
+    out["config"] = {"workload": f"poisson3d_{args.nx}",
+                     "matrix": f"3D Poisson 7-point {args.nx}^3, Dirichlet",
+                     "n": A.n, "nnz": A.nnz, "basis": "scaled_newton",
+                     "s_max": s_max, "restart": restart, "tol": tol,
+                     "rhs": "N(0,1) seed 2", "x0": "zero"}
+    for name in per:
+        out[name] = summary(name)
+    if "fp64" in per and "fp32_ir" in per:
+        out["fp32_ir"]["speedup_vs_fp64"] = round(
+            out["fp64"]["ms"] / out["fp32_ir"]["ms"], 3)
+
+    # roofline of the dominant kernel: float64 MPK SpMV
+    rs = infos[primary]
+    n_spmv = sum(r.info["n_spmv"] for r in rs)
+    t_spmv = sum(r.info["t_spmv_ms"] for r in rs)
+    avg_ms = t_spmv / max(1, n_spmv)
+    vb = 8 if primary == "fp64" else 4
+    alg_bytes = A.nnz * (vb + 4) + 4 * (A.n + 1) + 2 * vb * A.n
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    khash = spmv_source_hash()
+    out["roofline"] = {
+        "kernel": f"k_spmv<{'double' if vb == 8 else 'float'}, EPI_MPK> "
+                  "(SELL-C-64 SpMV of the matrix powers kernel)",
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": load_traffic(khash),
+        "algorithmic_bytes_per_launch": int(alg_bytes),
+        "avg_launch_us": round(avg_ms * 1e3, 2), "launches": int(n_spmv),
+        "spmv_source_sha256_16": khash}
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on one restart cycle (CPU)")
+        out["cpu_baseline"] = cpu_baseline(
+            A, b_host, out[primary]["iters"], restart, s_max)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -134,10 +134,15 @@ typedef struct {
   int32_t gamma_guard_hits; /* gamma_k raised by the zero guard              */
   double rel_res_true;    /* final ||b - A x|| / ||b - A x0|| (float64)      */
   double rel_res_est;     /* last Givens estimate                            */
-  double t_phase_ms[8];   /* host wall time: 0 setup, 1 pre-phase + shifts,
-                             2 MPK, 3 block orthogonalisation, 4 Hessenberg +
-                             Givens, 5 cycle end (update + true residual),
-                             6 refinement, 7 total                           */
+  double t_phase_ms[8];   /* 0 setup (host wall), 1 pre-phase + shifts (host
+                             wall), 2 MPK, 3 block orthogonalisation, 4
+                             Hessenberg + Givens (GPU time between HIP events
+                             on the solve's stream), 5 cycle end: update +
+                             true residual (host wall), 6 refinement loop
+                             (host wall), 7 total (host wall)                */
+  int64_t n_spmv;         /* SpMV launches of the matrix powers kernel       */
+  double t_spmv_ms;       /* their GPU time: one HIP event pair around the
+                             back-to-back launches of each block's MPK       */
 } sgm_info;
 
 /* Bytes of device workspace sgm_solve needs for this matrix and options. */

@@ -55,6 +55,7 @@ class Info(C.Structure):
         ("gamma_guard_hits", C.c_int32),
         ("rel_res_true", C.c_double), ("rel_res_est", C.c_double),
         ("t_phase_ms", C.c_double * 8),
+        ("n_spmv", C.c_int64), ("t_spmv_ms", C.c_double),
     ]
 
     def as_dict(self):

@@ -55,14 +55,11 @@ __device__ void eig2(double a, double b, double c, double d, double& r1,
   }
 }
 
-__global__ __launch_bounds__(kWave) void k_hqr(const double* __restrict__ Hin,
-                                               int ldh, int n, double* wr,
-                                               double* wi, double* scratch,
-                                               int* status) {
-  __shared__ double Hs[kHqrMax * kHqrMax];
+__device__ __forceinline__ void hqr_body(double* H, int ld,
+                                         const double* __restrict__ Hin,
+                                         int ldh, int n, double* wr,
+                                         double* wi, int* status) {
   const int lane = threadIdx.x;
-  double* H = n <= kHqrMax ? Hs : scratch;
-  const int ld = n <= kHqrMax ? kHqrMax : n;
   for (int e = lane; e < n * n; e += kWave) {
     const int r = e % n, c = e / n;
     at(H, ld, r, c) = r <= c + 1 ? Hin[(int64_t)c * ldh + r] : 0.0;
@@ -187,6 +184,20 @@ __global__ __launch_bounds__(kWave) void k_hqr(const double* __restrict__ Hin,
     }
   }
   if (lane == 0) *status = ok ? 0 : 1;
+}
+
+// One wavefront; the window lives in LDS up to order 128 (body instantiated
+// with the LDS array so its accesses compile to ds_* instructions), in
+// global scratch above.
+__global__ __launch_bounds__(kWave) void k_hqr(const double* __restrict__ Hin,
+                                               int ldh, int n, double* wr,
+                                               double* wi, double* scratch,
+                                               int* status) {
+  __shared__ double Hs[kHqrMax * kHqrMax];
+  if (n <= kHqrMax)
+    hqr_body(Hs, kHqrMax, Hin, ldh, n, wr, wi, status);
+  else
+    hqr_body(scratch, n, Hin, ldh, n, wr, wi, status);
 }
 
 // ------------------------------------------------------------------ Leja

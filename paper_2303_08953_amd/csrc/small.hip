@@ -12,17 +12,6 @@ namespace {
 
 constexpr int kSmallBlock = 256;
 
-__device__ double block_sum(double v, double* red) {
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  __syncthreads();
-  if (lane == 0) red[w] = v;
-  __syncthreads();
-  double t = 0.0;
-  for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += red[i];
-  return t;
-}
-
 // Largest eigenvalue of [[a, b], [b, c]] and a unit eigenvector (u, v).
 __device__ void top_eig_2x2(double a, double b, double c, double& lam,
                             double& u, double& v) {
@@ -38,101 +27,132 @@ __device__ void top_eig_2x2(double a, double b, double c, double& lam,
   v = y / nr;
 }
 
-// Partial Cholesky (Alg. 3) of the leading s x s block of G, right-looking
-// in place in the upper triangle of a work copy (LDS when s <= 128).  After
-// column j the incremental condition estimator updates its two approximate
-// singular vectors: y for the largest singular value (|y^T R|) and
-// d = R^{-T} x for the smallest (1/|d|), each through a 2x2 symmetric
-// eigenproblem in (sin, cos); the factorisation stops before a column whose
-// pivot is not positive and finite, or whose estimate exceeds omega.
-// Outputs: p, R (p x p upper), Rinv = R^{-1} (explicit, by column-wise back
-// substitution), both column-major with leading dimension ldr.
+// Partial Cholesky (Alg. 3) of the leading s x s block of G, right-looking,
+// in LDS (row-major work copy; thread k % nthr owns column k).  After the
+// pivot of column j the incremental condition estimator takes its step.
+// The estimator keeps unit approximate singular vectors y (largest singular
+// value, |y^T R|) and d = R^{-T} x (smallest, 1/|d|); column j's update is
+// a 2x2 symmetric eigenproblem in (sin, cos) that needs a = y^T R(0:j, j)
+// and a2 = d^T R(0:j, j).  Both are kept as running sums for every later
+// column k: when row j of R appears, P_k <- s1 P_k + c1 R(j, k) and
+// Q_k <- s2 Q_k + d_j R(j, k), which is exactly y^T R(0:j+1, k) and
+// d^T R(0:j+1, k) after the update y <- [s1 y; c1], d <- [s2 d; d_j].  No
+// reductions are needed; the owner of column j broadcasts (P_j, Q_j).
+// The factorisation stops before a column whose pivot is not positive and
+// finite or whose estimate exceeds omega.  Outputs: p, R (p x p upper),
+// Rinv = R^{-1} (explicit, column-wise back substitution in LDS), both
+// column-major with leading dimension ldr.
+constexpr int kPcholLds = 144 * 1024 / 8;
+constexpr int kPcholCols = 4;  // columns per thread: s <= 4 * blockDim.x
+
+// The body is instantiated twice: with the LDS array (every access then
+// compiles to a ds_* instruction) and with global scratch for large s.
+__device__ __forceinline__ void pchol_body(
+    double* Aw, double* bc, const double* __restrict__ G, int ldg, int s,
+    double omega, double* __restrict__ R, double* __restrict__ Rinv, int ldr,
+    int* p_out) {
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int la = s > 0 ? s : 1;
+  double* Ri = Aw + (size_t)s * s;
+  for (int e = tid; e < s * s; e += nthr) {
+    const int i = e % s, j = e / s;  // G symmetric: (i, j) -> row i, col j
+    Aw[i * la + j] = G[(int64_t)j * ldg + i];
+  }
+  double P[kPcholCols], Q[kPcholCols];
+#pragma unroll
+  for (int q = 0; q < kPcholCols; ++q) { P[q] = 0.0; Q[q] = 0.0; }
+  double smax2 = 0.0, dn2 = 0.0;  // uniform estimator state
+  int p = s;
+  __syncthreads();
+  for (int j = 0; j < s; ++j) {
+    const int owner = j % nthr, qj = j / nthr;
+    if (tid == owner) {
+      double pj = 0.0, qv = 0.0;
+#pragma unroll
+      for (int q = 0; q < kPcholCols; ++q)
+        if (q == qj) { pj = P[q]; qv = Q[q]; }
+      bc[0] = pj;
+      bc[1] = qv;
+    }
+    __syncthreads();
+    const double piv = Aw[j * la + j];
+    if (!(piv > 0.0) || !isfinite(piv)) { p = j; break; }
+    const double rjj = sqrt(piv);
+    double s1 = 0.0, c1 = 1.0, s2 = 0.0, c2 = 1.0, kappa = 1.0, a2 = 0.0;
+    const double r2 = rjj * rjj;
+    if (j == 0) {
+      smax2 = r2;
+      dn2 = 1.0 / r2;
+    } else {
+      const double a = bc[0];
+      a2 = bc[1];
+      double lam1, lam2;
+      top_eig_2x2(smax2 + a * a, a * rjj, r2, lam1, s1, c1);
+      top_eig_2x2(dn2 + (a2 / rjj) * (a2 / rjj), -a2 / r2, 1.0 / r2, lam2,
+                  s2, c2);
+      smax2 = lam1;
+      dn2 = lam2;
+      kappa = sqrt(smax2 * dn2);
+    }
+    if (!(kappa <= omega)) { p = j; break; }
+    const double dj = (c2 - s2 * a2) / rjj;
+    // row j of R and the running estimator sums of the owned columns
+#pragma unroll
+    for (int q = 0; q < kPcholCols; ++q) {
+      const int k = tid + q * nthr;
+      if (k > j && k < s) {
+        const double rjk = Aw[j * la + k] / rjj;
+        Aw[j * la + k] = rjk;
+        P[q] = s1 * P[q] + c1 * rjk;
+        Q[q] = s2 * Q[q] + dj * rjk;
+      }
+    }
+    if (tid == owner) Aw[j * la + j] = rjj;
+    __syncthreads();
+    // trailing update of the owned columns: A(l, k) -= R(j, l) R(j, k)
+#pragma unroll
+    for (int q = 0; q < kPcholCols; ++q) {
+      const int k = tid + q * nthr;
+      if (k > j && k < s) {
+        const double rjk = Aw[j * la + k];
+        for (int l = j + 1; l <= k; ++l) Aw[l * la + k] -= Aw[j * la + l] * rjk;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) *p_out = p;
+  // Rinv = R^{-1}: thread c owns column c (back substitution R x = e_c)
+  for (int c = tid; c < p; c += nthr) {
+    Ri[c * la + c] = 1.0 / Aw[c * la + c];
+    for (int r = c - 1; r >= 0; --r) {
+      double acc = 0.0;
+      for (int t = r + 1; t <= c; ++t) acc += Aw[r * la + t] * Ri[t * la + c];
+      Ri[r * la + c] = -acc / Aw[r * la + r];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < p * p; e += nthr) {
+    const int i = e % p, j = e / p;
+    const bool up = i <= j;
+    R[(int64_t)j * ldr + i] = up ? Aw[i * la + j] : 0.0;
+    Rinv[(int64_t)j * ldr + i] = up ? Ri[i * la + j] : 0.0;
+  }
+}
+
 __global__ __launch_bounds__(kSmallBlock) void k_pchol(
     const double* __restrict__ G, int ldg, int smax, const int* s_dev,
     double omega, double* __restrict__ R, double* __restrict__ Rinv, int ldr,
     int* p_out, double* scratch) {
-  __shared__ double As[kSmallLds * kSmallLds];
-  __shared__ double ys[1024], ds[1024];
-  __shared__ double red[kSmallBlock / kWave];
+  __shared__ double buf[kPcholLds];
   __shared__ double bc[4];
-  const int tid = threadIdx.x;
   int s = smax;
   if (s_dev) s = min(s, *s_dev);
-  if (s > 1024) s = 1024;
-  double* Aw = s <= kSmallLds ? As : scratch;
-  const int la = s <= kSmallLds ? (s > 0 ? s : 1) : smax;
-  for (int e = tid; e < s * s; e += kSmallBlock) {
-    const int i = e % s, j = e / s;
-    Aw[j * la + i] = G[(int64_t)j * ldg + i];
-  }
-  __syncthreads();
-  double smax2 = 0.0, dn2 = 0.0;  // estimator state (uniform across threads)
-  int p = s;
-  for (int j = 0; j < s; ++j) {
-    const double piv = Aw[j * la + j];
-    if (!(piv > 0.0) || !isfinite(piv)) { p = j; break; }
-    const double rjj = sqrt(piv);
-    double kappa = 1.0;
-    if (j == 0) {
-      if (tid == 0) { ys[0] = 1.0; ds[0] = 1.0 / rjj; }
-      smax2 = piv;
-      dn2 = 1.0 / piv;
-    } else {
-      double a = 0.0, a2 = 0.0;
-      for (int t = tid; t < j; t += kSmallBlock) {
-        const double v = Aw[j * la + t];  // R(t, j)
-        a += ys[t] * v;
-        a2 += v * ds[t];
-      }
-      a = block_sum(a, red);
-      a2 = block_sum(a2, red);
-      double lam1, s1, c1, lam2, s2, c2;
-      top_eig_2x2(smax2 + a * a, a * rjj, rjj * rjj, lam1, s1, c1);
-      top_eig_2x2(dn2 + (a2 / rjj) * (a2 / rjj), -a2 / (rjj * rjj),
-                  1.0 / (rjj * rjj), lam2, s2, c2);
-      smax2 = lam1;
-      dn2 = lam2;
-      kappa = sqrt(smax2 * dn2);
-      __syncthreads();
-      for (int t = tid; t < j; t += kSmallBlock) {
-        ys[t] *= s1;
-        ds[t] *= s2;
-      }
-      if (tid == 0) {
-        ys[j] = c1;
-        ds[j] = (c2 - s2 * a2) / rjj;
-      }
-    }
-    if (!(kappa <= omega)) { p = j; break; }
-    __syncthreads();
-    if (tid == 0) Aw[j * la + j] = rjj;
-    for (int k = j + 1 + tid; k < s; k += kSmallBlock) Aw[k * la + j] /= rjj;
-    __syncthreads();
-    const int rem = s - j - 1;
-    for (int e = tid; e < rem * rem; e += kSmallBlock) {
-      const int kk = j + 1 + e % rem, ll = j + 1 + e / rem;
-      if (kk <= ll) Aw[ll * la + kk] -= Aw[kk * la + j] * Aw[ll * la + j];
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  if (tid == 0) *p_out = p;
-  for (int e = tid; e < p * p; e += kSmallBlock) {
-    const int i = e % p, j = e / p;
-    R[(int64_t)j * ldr + i] = i <= j ? Aw[j * la + i] : 0.0;
-  }
-  __syncthreads();
-  // Rinv column c by back substitution: R x = e_c.
-  for (int c = tid; c < p; c += kSmallBlock) {
-    double* xc = Rinv + (int64_t)c * ldr;
-    for (int r = c + 1; r < p; ++r) xc[r] = 0.0;
-    xc[c] = 1.0 / Aw[c * la + c];
-    for (int r = c - 1; r >= 0; --r) {
-      double acc = 0.0;
-      for (int t = r + 1; t <= c; ++t) acc += Aw[t * la + r] * xc[t];
-      xc[r] = -acc / Aw[r * la + r];
-    }
-  }
+  // work layout: A (s x s, row-major) | Rinv (s x s, row-major)
+  if (2 * (size_t)s * s <= (size_t)kPcholLds)
+    pchol_body(buf, bc, G, ldg, s, omega, R, Rinv, ldr, p_out);
+  else
+    pchol_body(scratch, bc, G, ldg, s, omega, R, Rinv, ldr, p_out);
 }
 
 // Combine both BCGS passes (Alg. 4): R(1:i, k) = W(:, 1:p) + R2(:, 1:p) Z,
@@ -178,115 +198,328 @@ __global__ __launch_bounds__(kSmallBlock) void k_combine(
   }
 }
 
-// Hessenberg recovery for the block started at basis vector nb (1-based):
-// with Rt = [e_nb | R(1:nb+p, k)] and B the (p+1) x p change-of-basis matrix
-// of the recurrence records, H(1:nb+p, nb:nb+p-1) = (Rt B - [H(1:nb,
-// 1:nb-1) X; 0]) T^{-1}, X = Rt(1:nb-1, 1:p), T = Rt(nb:nb+p-1, 1:p).
-// Then the new columns get the earlier Givens rotations, new rotations are
-// formed column by column, and the relative residual estimate
-// |g(c+1)| / beta0 of every new column is written to res_out; the block
-// stops at the first column that meets tol.
-__global__ __launch_bounds__(kSmallBlock) void k_hess_givens(
+// C(m x n) = (add ? C : 0) + alpha A(m x k) B(k x n), all column-major in
+// LDS or global memory, by the whole workgroup with 4 x 4 register tiles
+// (every A and B element feeds 4 multiply-adds from registers).  Thread t
+// takes rows rg, rg + RG, rg + 2 RG, rg + 3 RG (rg = t % RG, RG = the number
+// of row groups) so that neighbouring threads read neighbouring rows, and
+// columns 4 cg .. 4 cg + 3 (cg = t / RG).
+__device__ __forceinline__ void tile_gemm(int m, int n, int k,
+                                          const double* A, int lda,
+                                          const double* B, int ldb, double* C,
+                                          int ldc, double alpha, bool add) {
+  const int RG = (m + 3) / 4, CG = (n + 3) / 4;
+  for (int t = threadIdx.x; t < RG * CG; t += blockDim.x) {
+    const int rg = t % RG, c0 = (t / RG) * 4;
+    // out-of-range rows / columns read row / column 0 and are not stored
+    const double* ap[4];
+    const double* bp[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int r = rg + i * RG;
+      ap[i] = A + (r < m ? r : 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      bp[j] = B + (size_t)(c0 + j < n ? c0 + j : 0) * ldb;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+#pragma unroll 2
+    for (int kk = 0; kk < k; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        a[i] = *ap[i];
+        ap[i] += lda;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = bp[j][kk];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = rg + i * RG;
+        if (r < m && c0 + j < n) {
+          double* cp = C + (size_t)(c0 + j) * ldc + r;
+          *cp = (add ? *cp : 0.0) + alpha * acc[i][j];
+        }
+      }
+  }
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Fused tail of one block (one workgroup).
+//  1. Combine the BCGS passes (Alg. 4): R(1:nb, k) = W + R2 Z and
+//     R(k, k) = Zt Z (Z, Zt upper triangular).
+//  2. Hessenberg recovery: with Rt = [e_nb | R(1:nb+p, k)] and the
+//     (p+1) x p change-of-basis matrix B of the recurrence records,
+//     H(1:nb+p, nb:nb+p-1) = (Rt B - [H(1:nb, 1:nb-1) X; 0]) T^{-1},
+//     X = Rt(1:nb-1, :), T = Rt(nb:nb+p-1, :) = [1 a^T; 0 R(k,k)'] where
+//     R(k,k)' is the leading (p-1) block, so T^{-1} = [1 -a^T K; 0 K] with
+//     K = R(k,k)'^{-1} = (Z^{-1} Zt^{-1})' from the two explicit inverses.
+//  3. Givens: the earlier rotations on the new columns, then the new ones in
+//     order with the relative residual estimate |g(c+1)| / beta0 and the
+//     convergence test after every column.
+// Work in LDS (global scratch when it does not fit); the small products are
+// register-tiled; the rotation sweeps run on wavefront 0 with each lane
+// owning whole columns.  A breakdown (p2 = 0) yields one column with a zero
+// subdiagonal.
+constexpr int kTailLds = 150 * 1024 / 8;
+
+// doubles of the work area:
+//   Rt_top nb*p | Rkk p*p | Tinv p*p | union(R2 nb*p, Z, Zt, Zi, Zti p*p
+//   each ; Mb nr*p) | Hn nr*p | css nb | sns nb | gs p+1 | pad
+// The union's inputs are dead once step 1 has finished.
+__host__ __device__ inline size_t tail_union(int nb, int p) {
+  const size_t a = (size_t)nb * p + 4 * (size_t)p * p;
+  const size_t b = (size_t)(nb + p) * p;
+  return a > b ? a : b;
+}
+__host__ __device__ inline size_t tail_doubles(int nb, int p) {
+  return (size_t)nb * p + 2 * (size_t)p * p + tail_union(nb, p) +
+         (size_t)(nb + p) * p + 2 * (size_t)nb + (size_t)p + 16;
+}
+
+__device__ __forceinline__ void tail_body(
+    double* base, int* sh, const double* __restrict__ W,
+    const double* __restrict__ R2g, int ldw, const double* __restrict__ Zg,
+    const double* __restrict__ Ztg, const double* __restrict__ Zig,
+    const double* __restrict__ Ztig, int ldz, int nb, int* ctrl,
+    double* __restrict__ Rtop_out, double* __restrict__ Rkk_out,
     double* __restrict__ Hraw, double* __restrict__ Hr, int ldh,
     double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
-    int nb, const double* __restrict__ Rtop, int ldt,
-    const double* __restrict__ Rkk, int ldk, const double* __restrict__ rec,
-    int n_rec, const double* __restrict__ beta0, double tol, int* ctrl,
+    const double* __restrict__ rec, int n_rec,
+    const double* __restrict__ beta0, double tol,
     double* __restrict__ res_out) {
-  const int p = ctrl[C_PH];
+  int& kdone_s = sh[0];
+  int& conv_s = sh[1];
+  int& bad_s = sh[2];
   const int tid = threadIdx.x;
-  const int i0 = nb - 1;  // 0-based row of e_nb in Rt; first new column
-  auto Rt = [&](int r, int c) -> double {  // (nb+p) x (p+1)
-    if (c == 0) return r == i0 ? 1.0 : 0.0;
-    if (r < nb) return Rtop[(int64_t)(c - 1) * ldt + r];
-    return Rkk[(int64_t)(c - 1) * ldk + (r - nb)];
-  };
-  // Each thread owns rows of the new block of H; the row solve with T is
-  // independent per row.
-  for (int r = tid; r < nb + p; r += kSmallBlock) {
-    double* hrow = Hraw + r;  // element (r, c) at hrow[c * ldh]
-    for (int j = 0; j < p; ++j) {
-      const int q = j % n_rec;
-      const double th = rec[3 * q], ga = rec[3 * q + 1], de = rec[3 * q + 2];
-      double m = th * Rt(r, j) + ga * Rt(r, j + 1);
-      if (j >= 1) m += de * Rt(r, j - 1);
-      if (r < nb && nb > 1) {
-        double acc = 0.0;
-        for (int t = 0; t < nb - 1; ++t)
-          acc += Hraw[(int64_t)t * ldh + r] * Rt(t, j);
-        m -= acc;
-      }
-      // forward substitution with T (T(a, b) = Rt(i0 + a, b))
-      for (int t = 0; t < j; ++t) m -= hrow[(int64_t)(i0 + t) * ldh] * Rt(i0 + t, j);
-      hrow[(int64_t)(i0 + j) * ldh] = m / Rt(i0 + j, j);
-    }
+  const int p1 = ctrl[C_P1], p2 = ctrl[C_P2];
+  const bool brk = p2 == 0;
+  const int p = brk ? 1 : p2;
+  const int pz = brk ? (p1 > 0 ? 1 : 0) : p;  // columns of R2 / Z used
+  const int i0 = nb - 1;
+  const int nr = nb + p;  // rows of the new block
+  double* Rt_top = base;                   // nb x p
+  double* Rkk = Rt_top + (size_t)nb * p;   // p x p
+  double* Tinv = Rkk + (size_t)p * p;      // p x p
+  double* uni = Tinv + (size_t)p * p;
+  double* R2 = uni;                        // nb x p
+  double* Z = R2 + (size_t)nb * p;         // p x p each
+  double* Zt = Z + (size_t)p * p;
+  double* Zi = Zt + (size_t)p * p;
+  double* Zti = Zi + (size_t)p * p;
+  double* Mb = uni;                        // nr x p (after step 1)
+  double* Hn = uni + tail_union(nb, p);    // nr x p
+  double* css = Hn + (size_t)nr * p;
+  double* sns = css + nb;
+  double* gs = sns + nb;
+  // 0. stage the inputs (coalesced); Z, Zt, Zi, Zti zero-padded to p x p
+  for (int e = tid; e < nb * p; e += kSmallBlock) {
+    const int r = e % nb, c = e / nb;
+    R2[(size_t)c * nb + r] = c < pz && p1 > 0 ? R2g[(int64_t)c * ldw + r] : 0.0;
   }
-  __syncthreads();
-  // Rotated copy of the new columns (rows 0..c+1 only) with the rotations
-  // of earlier blocks applied; one thread per column.
-  for (int j = tid; j < p; j += kSmallBlock) {
-    const int c = i0 + j;
-    double* h = Hr + (int64_t)c * ldh;
-    for (int r = 0; r <= c + 1; ++r) h[r] = Hraw[(int64_t)c * ldh + r];
-    for (int r = 0; r < i0; ++r) {
-      const double a = h[r], b = h[r + 1];
-      h[r] = cs[r] * a + sn[r] * b;
-      h[r + 1] = -sn[r] * a + cs[r] * b;
-    }
+  for (int e = tid; e < p * p; e += kSmallBlock) {
+    const int r = e % p, c = e / p;
+    const bool in = r < pz && c < pz;
+    const bool in2 = !brk && r < p && c < p;
+    Z[(size_t)c * p + r] = in ? Zg[(int64_t)c * ldz + r] : 0.0;
+    Zt[(size_t)c * p + r] = in2 ? Ztg[(int64_t)c * ldz + r] : 0.0;
+    Zi[(size_t)c * p + r] = in2 ? Zig[(int64_t)c * ldz + r] : 0.0;
+    Zti[(size_t)c * p + r] = in2 ? Ztig[(int64_t)c * ldz + r] : 0.0;
   }
-  __syncthreads();
-  // Rotations of this block, in order.
-  __shared__ int stop;
-  if (tid == 0) stop = 0;
-  __syncthreads();
-  int kdone = p, conv = 0, bad = 0;
-  for (int j = 0; j < p; ++j) {
-    const int c = i0 + j;
-    double* h = Hr + (int64_t)c * ldh;
-    if (tid == 0) {
-      const double a = h[c], b = h[c + 1];
-      double cc, ss, rr;
-      if (b == 0.0) {
-        cc = 1.0; ss = 0.0; rr = a;
-      } else {
-        rr = hypot(a, b);
-        cc = a / rr;
-        ss = b / rr;
-      }
-      cs[c] = cc;
-      sn[c] = ss;
-      h[c] = rr;
-      h[c + 1] = 0.0;
-      const double gc = g[c];
-      g[c] = cc * gc;
-      g[c + 1] = -ss * gc;
-      const double res = fabs(g[c + 1]) / beta0[0];
-      res_out[j] = res;
-      if (!isfinite(res)) stop = 2;
-      else if (res <= tol) stop = 1;
-    }
-    __syncthreads();
-    if (stop) {
-      kdone = j + 1;
-      conv = stop == 1;
-      bad = stop == 2;
-      break;
-    }
-    // apply rotation c to the later columns of the block
-    const double cc = cs[c], ss = sn[c];
-    for (int jj = j + 1 + tid; jj < p; jj += kSmallBlock) {
-      double* h2 = Hr + (int64_t)(i0 + jj) * ldh;
-      const double a = h2[c], b = h2[c + 1];
-      h2[c] = cc * a + ss * b;
-      h2[c + 1] = -ss * a + cc * b;
-    }
-    __syncthreads();
+  for (int e = tid; e < nb * p; e += kSmallBlock) {
+    const int r = e % nb, c = e / nb;
+    Rt_top[(size_t)c * nb + r] = W[(int64_t)c * ldw + r];
+  }
+  for (int r = tid; r < i0; r += kSmallBlock) {
+    css[r] = cs[r];
+    sns[r] = sn[r];
   }
   if (tid == 0) {
-    ctrl[C_KDONE] = kdone;
-    ctrl[C_CONV] = conv;
-    ctrl[C_BAD] = bad;
+    ctrl[C_PH] = p;
+    ctrl[C_BREAK] = brk ? 1 : 0;
   }
+  __syncthreads();
+  // 1. combine: Rt_top = W + R2 Z, Rkk = Zt Z
+  tile_gemm(nb, p, p, R2, nb, Z, p, Rt_top, nb, 1.0, true);
+  tile_gemm(p, p, p, Zt, p, Z, p, Rkk, p, 1.0, false);
+  // K = (Zi Zti)' into Tinv(1:p, 1:p)
+  if (p > 1) tile_gemm(p - 1, p - 1, p - 1, Zi, p, Zti, p, Tinv + p + 1, p,
+                       1.0, false);
+  __syncthreads();
+  if (Rtop_out)
+    for (int e = tid; e < nb * p; e += kSmallBlock) {
+      const int r = e % nb, c = e / nb;
+      Rtop_out[(int64_t)c * ldw + r] = Rt_top[(size_t)c * nb + r];
+    }
+  if (Rkk_out)
+    for (int e = tid; e < p * p; e += kSmallBlock) {
+      const int r = e % p, c = e / p;
+      Rkk_out[(int64_t)c * ldz + r] = Rkk[(size_t)c * p + r];
+    }
+  // first row and column of T^{-1}: [1, -a^T K], a = Rt(i0, 1:p-1)
+  for (int c = tid; c < p; c += kSmallBlock) {
+    double v;
+    if (c == 0) {
+      v = 1.0;
+    } else {
+      double acc = 0.0;
+      for (int t = 0; t < p - 1; ++t)
+        acc += Rt_top[(size_t)t * nb + i0] * Tinv[(size_t)c * p + 1 + t];
+      v = -acc;
+    }
+    Tinv[(size_t)c * p] = v;
+    if (c > 0) Tinv[c] = 0.0;
+  }
+  auto Rt = [&](int r, int c) -> double {  // nr x (p + 1)
+    if (c == 0) return r == i0 ? 1.0 : 0.0;
+    if (r < nb) return Rt_top[(size_t)(c - 1) * nb + r];
+    return Rkk[(size_t)(c - 1) * p + (r - nb)];
+  };
+  // 2. M = Rt B (tridiagonal B from the records), then M(1:nb, 2:p) -= H X
+  for (int e = tid; e < nr * p; e += kSmallBlock) {
+    const int r = e % nr, j = e / nr;
+    const int q = j % n_rec;
+    const double th = rec[3 * q], ga = rec[3 * q + 1], de = rec[3 * q + 2];
+    double m = th * Rt(r, j) + ga * Rt(r, j + 1);
+    if (j >= 1) m += de * Rt(r, j - 1);
+    Mb[(size_t)j * nr + r] = m;
+  }
+  __syncthreads();
+  if (nb > 1 && p > 1)
+    tile_gemm(nb, p - 1, i0, Hraw, ldh, Rt_top, nb, Mb + nr, nr, -1.0, true);
+  __syncthreads();
+  // Hn = M T^{-1}; write the new columns of H
+  tile_gemm(nr, p, p, Mb, nr, Tinv, p, Hn, nr, 1.0, false);
+  __syncthreads();
+  for (int e = tid; e < nr * p; e += kSmallBlock) {
+    const int r = e % nr, j = e / nr;
+    Hraw[(int64_t)(i0 + j) * ldh + r] = Hn[(size_t)j * nr + r];
+  }
+  // 3. rotations on wavefront 0: lane l owns columns l, l + 64, ...
+  if (tid < kWave) {
+    const int lane = tid;
+    // earlier rotations on every new column (rows <= c + 1 only); the
+    // rotated pair's lower entry is carried in a register
+    for (int j = lane; j < p; j += kWave) {
+      double* h = Hn + (size_t)j * nr;
+      if (i0 > 0) {
+        double carry = h[0];
+        for (int r = 0; r < i0; ++r) {
+          const double b = h[r + 1], c0 = css[r], s0 = sns[r];
+          h[r] = c0 * carry + s0 * b;
+          carry = -s0 * carry + c0 * b;
+        }
+        h[i0] = carry;
+      }
+    }
+    // new rotations in order; g's running entry gcur is uniform
+    double gcur = g[i0];
+    const double b0 = beta0[0];
+    int kdone = p, conv = 0, bad = 0;
+    for (int j = 0; j < p; ++j) {
+      const int c = i0 + j;
+      const int owner = j % kWave;
+      double cc = 1.0, ss = 0.0;
+      if (lane == owner) {
+        double* h = Hn + (size_t)j * nr;
+        const double a = h[c], b = h[c + 1];
+        double rr;
+        if (b == 0.0) {
+          rr = a;
+        } else {
+          rr = hypot(a, b);
+          cc = a / rr;
+          ss = b / rr;
+        }
+        h[c] = rr;
+        h[c + 1] = 0.0;
+      }
+      cc = readlane_f64(cc, owner);
+      ss = readlane_f64(ss, owner);
+      const double gnew = -ss * gcur;
+      const double res = fabs(gnew) / b0;
+      if (lane == 0) {
+        cs[c] = cc;
+        sn[c] = ss;
+        gs[j] = cc * gcur;
+        res_out[j] = res;
+      }
+      gcur = gnew;
+      if (!isfinite(res) || res <= tol) {
+        kdone = j + 1;
+        conv = isfinite(res) ? 1 : 0;
+        bad = isfinite(res) ? 0 : 1;
+        break;
+      }
+      for (int jj = lane; jj < p; jj += kWave) {
+        if (jj <= j) continue;
+        double* h2 = Hn + (size_t)jj * nr;
+        const double a = h2[c], b = h2[c + 1];
+        h2[c] = cc * a + ss * b;
+        h2[c + 1] = -ss * a + cc * b;
+      }
+    }
+    if (lane == 0) {
+      gs[kdone] = gcur;
+      kdone_s = kdone;
+      conv_s = conv;
+      bad_s = bad;
+    }
+  }
+  __syncthreads();
+  const int kdone = kdone_s;
+  // write back the rotated columns (rows <= c + 1) and g
+  for (int e = tid; e < kdone * nr; e += kSmallBlock) {
+    const int j = e / nr, r = e % nr;
+    const int c = i0 + j;
+    if (r <= c + 1) Hr[(int64_t)c * ldh + r] = Hn[(size_t)j * nr + r];
+  }
+  for (int r = tid; r <= kdone; r += kSmallBlock) g[i0 + r] = gs[r];
+  if (tid == 0) {
+    ctrl[C_KDONE] = kdone;
+    ctrl[C_CONV] = conv_s;
+    ctrl[C_BAD] = bad_s;
+  }
+}
+
+__global__ __launch_bounds__(kSmallBlock) void k_block_tail(
+    const double* __restrict__ W, const double* __restrict__ R2g, int ldw,
+    const double* __restrict__ Zg, const double* __restrict__ Ztg,
+    const double* __restrict__ Zig, const double* __restrict__ Ztig, int ldz,
+    int nb, int* ctrl, double* __restrict__ Rtop_out,
+    double* __restrict__ Rkk_out, double* __restrict__ Hraw,
+    double* __restrict__ Hr, int ldh, double* __restrict__ cs,
+    double* __restrict__ sn, double* __restrict__ g,
+    const double* __restrict__ rec, int n_rec,
+    const double* __restrict__ beta0, double tol, double* __restrict__ res_out,
+    double* scratch) {
+  __shared__ double lds[kTailLds];
+  __shared__ int sh[4];
+  const int p = ctrl[C_P2] == 0 ? 1 : ctrl[C_P2];
+  if (tail_doubles(nb, p) <= (size_t)kTailLds)
+    tail_body(lds, sh, W, R2g, ldw, Zg, Ztg, Zig, Ztig, ldz, nb, ctrl,
+              Rtop_out, Rkk_out, Hraw, Hr, ldh, cs, sn, g, rec, n_rec, beta0,
+              tol, res_out);
+  else
+    tail_body(scratch, sh, W, R2g, ldw, Zg, Ztg, Zig, Ztig, ldz, nb, ctrl,
+              Rtop_out, Rkk_out, Hraw, Hr, ldh, cs, sn, g, rec, n_rec, beta0,
+              tol, res_out);
 }
 
 // y = Hr(0:k, 0:k)^{-1} g(0:k), column-oriented back substitution.
@@ -320,7 +553,12 @@ __global__ void k_givens_init(double* g, int m, const double* beta) {
 void pchol_ice(const double* G, int ldg, int smax, const int* s_dev,
                double omega, double* R, double* Rinv, int ldr, int* p_out,
                double* scratch, hipStream_t st) {
-  hipLaunchKernelGGL(k_pchol, dim3(1), dim3(kSmallBlock), 0, st, G, ldg, smax,
+  // one wavefront (barriers are nearly free) unless the trailing updates
+  // are large enough to need more lanes
+  const int threads = smax <= 64 ? kWave : kSmallBlock;
+  if (smax > kPcholCols * threads)
+    throw Error{SGM_EINVAL, "partial Cholesky: block larger than 1024"};
+  hipLaunchKernelGGL(k_pchol, dim3(1), dim3(threads), 0, st, G, ldg, smax,
                      s_dev, omega, R, Rinv, ldr, p_out, scratch);
   SGM_CHECK_LAUNCH();
 }
@@ -333,14 +571,19 @@ void combine_r(const double* W, int ldw, const double* R2, int ldr2,
   SGM_CHECK_LAUNCH();
 }
 
-void hess_givens(double* Hraw, double* Hr, int ldh, double* cs, double* sn,
-                 double* g, int nb, const double* Rtop, int ldt,
-                 const double* Rkk, int ldk, const double* rec, int n_rec,
-                 const double* beta0, double tol, int* ctrl, double* res_out,
-                 double* /*scratch*/, hipStream_t st) {
-  hipLaunchKernelGGL(k_hess_givens, dim3(1), dim3(kSmallBlock), 0, st, Hraw,
-                     Hr, ldh, cs, sn, g, nb, Rtop, ldt, Rkk, ldk, rec, n_rec,
-                     beta0, tol, ctrl, res_out);
+size_t block_tail_scratch_doubles(int nb_max, int s_max) {
+  return tail_doubles(nb_max, s_max);
+}
+
+void block_tail(const double* W, const double* R2, int ldw, const double* Z,
+                const double* Zt, const double* Zi, const double* Zti, int ldz,
+                int nb, int* ctrl, double* Rtop, double* Rkk, double* Hraw,
+                double* Hr, int ldh, double* cs, double* sn, double* g,
+                const double* rec, int n_rec, const double* beta0, double tol,
+                double* res_out, double* scratch, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_tail, dim3(1), dim3(kSmallBlock), 0, st, W, R2,
+                     ldw, Z, Zt, Zi, Zti, ldz, nb, ctrl, Rtop, Rkk, Hraw, Hr,
+                     ldh, cs, sn, g, rec, n_rec, beta0, tol, res_out, scratch);
   SGM_CHECK_LAUNCH();
 }
 

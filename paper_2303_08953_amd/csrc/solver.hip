@@ -46,6 +46,7 @@ struct Work {
   double *rec = nullptr, *mono = nullptr;
   double *wr = nullptr, *wi = nullptr, *ritz = nullptr;
   double *hqr_scr = nullptr, *leja_scr = nullptr, *pchol_scr = nullptr;
+  double* tail_scr = nullptr;
   double* scal = nullptr;  // 0 beta0, 1 beta (current), 2 one
   int* ctrl = nullptr;     // C_NCTRL
   int* info = nullptr;     // 0 hqr status, 1..3 leja info
@@ -102,7 +103,8 @@ void layout(Arena& a, Work& w, int64_t n, int64_t sell_nnz, int m, int smax,
   w.ritz = a.take<double>(2 * nr);
   w.hqr_scr = a.take<double>((int64_t)nr * nr);
   w.leja_scr = a.take<double>((int64_t)shifts_scratch_doubles(nr));
-  w.pchol_scr = a.take<double>(ss);
+  w.pchol_scr = a.take<double>(2 * ss + 2 * smax);
+  w.tail_scr = a.take<double>((int64_t)block_tail_scratch_doubles(m + 1, smax));
   w.scal = a.take<double>(8);
   w.ctrl = a.take<int>(C_NCTRL + 1);
   w.info = a.take<int>(8);
@@ -141,7 +143,7 @@ double ms_since(Clock::time_point t) {
 // them, so the sequence needs no host synchronisation.
 template <typename T>
 void orth_block(T* Q, int64_t ld, int64_t nrows, int nb, int s, double omega,
-                Work& w, hipStream_t st) {
+                Work& w, hipStream_t st, bool combine = true) {
   T* V = Q + (int64_t)nb * ld;
   int* p1 = w.ctrl + C_P1;
   int* p2 = w.ctrl + C_P2;
@@ -161,8 +163,9 @@ void orth_block(T* Q, int64_t ld, int64_t nrows, int nb, int s, double omega,
   pchol_ice(w.G2, w.lds, s, p1, omega, w.Zt, w.Ztinv, w.lds, p2, w.pchol_scr,
             st);
   trsm_inv<T>(V, ld, s, w.Ztinv, w.lds, p2, nrows, st);
-  combine_r(w.W, w.ldw, w.R2, w.ldw, w.Z, w.Zt, w.lds, nb, w.ctrl, w.Rtop,
-            w.ldw, w.Rkk, w.lds, st);
+  if (combine)
+    combine_r(w.W, w.ldw, w.R2, w.ldw, w.Z, w.Zt, w.lds, nb, w.ctrl, w.Rtop,
+              w.ldw, w.Rkk, w.lds, st);
 }
 
 struct Shifts {
@@ -182,6 +185,8 @@ struct Result {
   std::vector<int> s_hist;
   double t[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   int s0 = 0, s_init = 0, n_rec = 0, hits = 0;
+  int64_t n_spmv = 0;
+  double t_spmv = 0.0;
 };
 
 template <typename T>
@@ -304,11 +309,11 @@ struct Engine {
       spmv_mpk<T>(S, vals, col(nb - 1 + j), xprev, col(nb + j), rec, q, st);
     }
     SGM_HIP(hipEventRecord(ev[1], st));
-    orth_block<T>(Q(), ld, ld, nb, s_eff, omega, w, st);
+    orth_block<T>(Q(), ld, ld, nb, s_eff, omega, w, st, false);
     SGM_HIP(hipEventRecord(ev[2], st));
-    hess_givens(w.Hraw, w.Hr, w.ldh, w.cs, w.sn, w.g, nb, w.Rtop, w.ldw,
-                w.Rkk, w.lds, rec, nrec, beta0, tol, w.ctrl, w.res_blk,
-                nullptr, st);
+    block_tail(w.W, w.R2, w.ldw, w.Z, w.Zt, w.Zinv, w.Ztinv, w.lds, nb,
+               w.ctrl, nullptr, nullptr, w.Hraw, w.Hr, w.ldh, w.cs, w.sn, w.g,
+               rec, nrec, beta0, tol, w.res_blk, w.tail_scr, st);
     SGM_HIP(hipEventRecord(ev[3], st));
     SGM_HIP(hipMemcpyAsync(hm.ctrl, w.ctrl, sizeof(int) * C_NCTRL,
                            hipMemcpyDeviceToHost, st));
@@ -322,6 +327,9 @@ struct Engine {
     res.t[2] += t01;
     res.t[3] += t12;
     res.t[4] += t23;
+    // the MPK launches run back to back between ev[0] and ev[1]
+    res.t_spmv += t01;
+    res.n_spmv += s_eff;
     BlockOut b;
     b.p2 = hm.ctrl[C_P2];
     b.ph = hm.ctrl[C_PH];
@@ -617,7 +625,7 @@ void block_layout(Arena& a, Work& w, int i, int s) {
   w.Zt = a.take<double>(ss);
   w.Ztinv = a.take<double>(ss);
   w.Rkk = a.take<double>(ss);
-  w.pchol_scr = a.take<double>(ss);
+  w.pchol_scr = a.take<double>(2 * ss + 2 * s);
   w.ctrl = a.take<int>(C_NCTRL + 1);
 }
 
@@ -798,6 +806,8 @@ sgm_status sgm_solve(sgm_matrix A, const double* b, const double* x0,
     info->rel_res_true = R.rel_true;
     info->rel_res_est = R.rel_est;
     for (int i = 0; i < 8; ++i) info->t_phase_ms[i] = R.t[i];
+    info->n_spmv = R.n_spmv;
+    info->t_spmv_ms = R.t_spmv;
   }
   if (st < 0) set_error(err);
   return st;

@@ -150,22 +150,44 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(
   for (int i = 0; i < MT; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = vzero<V>();
+  // M tiles with no valid column contribute nothing: skip their MFMAs
+  const int mt_live = min(MT, (ma - m0 + 15) / 16);
 
-  for (int64_t bt = b0 + wave; bt < b1; bt += kBlock / kWave) {
+  // Register double buffering: the loads of the next batch are in flight
+  // while the MFMAs of the current one run.
+  constexpr int kStep = kBlock / kWave;
+  V af[MT], bf[NT], an[MT], bn[NT];
+  // Loads are unconditional and unmasked: a column past the end reads
+  // column 0 instead; it only feeds output rows that are never stored or
+  // output columns that are zeroed at the store.  With no branch or select
+  // between a load and its MFMA, the compiler waits for the current batch
+  // only while the next one is in flight.
+  auto load = [&](int64_t bt, V (&a)[MT], V (&b)[NT]) {
     const int64_t row = bt * 16;
-    V af[MT], bf[NT];
 #pragma unroll
-    for (int i = 0; i < MT; ++i)
-      af[i] = va[i] ? *reinterpret_cast<const V*>(pa[i] + row) : vzero<V>();
+    for (int i = 0; i < MT; ++i) a[i] = *reinterpret_cast<const V*>(pa[i] + row);
 #pragma unroll
-    for (int j = 0; j < NT; ++j)
-      bf[j] = vb[j] ? *reinterpret_cast<const V*>(pb[j] + row) : vzero<V>();
+    for (int j = 0; j < NT; ++j) b[j] = *reinterpret_cast<const V*>(pb[j] + row);
+  };
+  int64_t bt = b0 + wave;
+  if (bt < b1) load(bt, af, bf);
+  for (; bt < b1; bt += kStep) {
+    const bool more = bt + kStep < b1;
+    if (more) load(bt + kStep, an, bn);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int i = 0; i < MT; ++i)
+      for (int i = 0; i < MT; ++i) {
+        if (i >= mt_live) continue;
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[i][j] = mfma(af[i][t], bf[j][t], acc[i][j]);
+      }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < MT; ++i) af[i] = an[i];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) bf[j] = bn[j];
+    }
   }
 
   // Fixed-order reduction of the 4 wavefronts through LDS.
@@ -199,25 +221,63 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(
           const int row = m0 + i * 16 + drow<T>(g, q);
           const int col = n0 + j * 16 + c16;
           if (row < ma && col < nb)
-            out[(int64_t)col * ma + row] = (double)acc[i][j][q] + red[e];
+            out[(int64_t)col * ma + row] =
+                col < nbe ? (double)acc[i][j][q] + red[e] : 0.0;
         }
   }
 }
 
 // C(i, j) = sum over chunks of part[c][j * ma + i]; with sym, entries below
-// the diagonal 16x16 tiles are read from the mirrored upper entry.
-__global__ void k_reduce_chunks(const double* __restrict__ part,
-                                int64_t nchunks, int ma, int nb,
-                                double* __restrict__ C, int ldc, int sym) {
-  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (e >= (int64_t)ma * nb) return;
-  const int i = (int)(e % ma), j = (int)(e / ma);
-  int64_t src = e;
-  if (sym && (i / 16) > (j / 16)) src = (int64_t)i * ma + j;
-  const int64_t stride = (int64_t)ma * nb;
+// the diagonal 16x16 tiles are read from the mirrored upper entry.  One
+// workgroup of 16 wavefronts per 64 consecutive outputs: wavefront w sums
+// the chunks c = w, w + 16, ... (lane = output, so every load is a
+// contiguous 64-element run), then the 16 partial sums are added in a fixed
+// order through LDS.  Deterministic.
+constexpr int kRedWaves = 16;
+
+__global__ __launch_bounds__(kRedWaves * kWave) void k_reduce_chunks(
+    const double* __restrict__ part, int64_t nchunks, int ma, int nb,
+    double* __restrict__ C, int ldc, int sym) {
+  __shared__ double red[kRedWaves][kWave];
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int64_t e = (int64_t)blockIdx.x * kWave + lane;
+  const int64_t ne = (int64_t)ma * nb;
+  const int64_t stride = ne;
   double s = 0.0;
-  for (int64_t c = 0; c < nchunks; ++c) s += part[c * stride + src];
-  C[(int64_t)j * ldc + i] = s;
+  int64_t src = e;
+  if (e < ne) {
+    const int i = (int)(e % ma), j = (int)(e / ma);
+    if (sym && (i / 16) > (j / 16)) src = (int64_t)i * ma + j;
+    int64_t c = w;
+    for (; c + 3 * kRedWaves < nchunks; c += 4 * kRedWaves) {
+      const double a0 = part[c * stride + src];
+      const double a1 = part[(c + kRedWaves) * stride + src];
+      const double a2 = part[(c + 2 * kRedWaves) * stride + src];
+      const double a3 = part[(c + 3 * kRedWaves) * stride + src];
+      s += a0;
+      s += a1;
+      s += a2;
+      s += a3;
+    }
+    for (; c < nchunks; c += kRedWaves) s += part[c * stride + src];
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && e < ne) {
+    double t = 0.0;
+    for (int q = 0; q < kRedWaves; ++q) t += red[q][lane];
+    const int i = (int)(e % ma), j = (int)(e / ma);
+    C[(int64_t)j * ldc + i] = t;
+  }
+}
+
+void launch_reduce(const double* part, int64_t nchunks, int ma, int nb,
+                   double* C, int ldc, int sym, hipStream_t st) {
+  const int64_t ne = (int64_t)ma * nb;
+  hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)ceil_div(ne, kWave)),
+                     dim3(kRedWaves * kWave), 0, st, part, nchunks, ma, nb, C,
+                     ldc, sym);
+  SGM_CHECK_LAUNCH();
 }
 
 // ------------------------------------------------------------- update / trsm
@@ -303,18 +363,10 @@ __global__ __launch_bounds__(kBlock) void k_update(
       }
       const int kend = min(kc, ka4 - k0);
       if (active) {
-        for (int kk = 0; kk < kend; kk += 4) {
-          const int k = k0 + kk + g;
-          T a[MT];
-          if (k < kae) {
-            load_rows<T, MT>((MODE == MODE_TRSM ? (const T*)B : A) +
-                                 (int64_t)k * (MODE == MODE_TRSM ? ldb : lda) +
-                                 r0 + MT * c16,
-                             a);
-          } else {
-#pragma unroll
-            for (int t = 0; t < MT; ++t) a[t] = 0;
-          }
+        const T* src = MODE == MODE_TRSM ? (const T*)B : A;
+        const int64_t lds_ = MODE == MODE_TRSM ? ldb : lda;
+        const T* base = src + r0 + MT * c16;
+        auto kstep = [&](int kk, const T (&a)[MT]) {
           const T* mrow = Ms + (kk + g) * W16 + c16;
 #pragma unroll
           for (int j = 0; j < NT; ++j) {
@@ -323,6 +375,52 @@ __global__ __launch_bounds__(kBlock) void k_update(
 #pragma unroll
             for (int t = 0; t < MT; ++t) acc[t][j] = mfma(a[t], bv, acc[t][j]);
           }
+        };
+        // unconditional loads: a column past the end reads column 0, whose
+        // staged M row is zero, so no branch or select splits the
+        // outstanding loads
+        auto kload = [&](int kk, T (&a)[MT]) {
+          const int k = k0 + kk + g;
+          load_rows<T, MT>(base + (int64_t)(k < kae ? k : 0) * lds_, a);
+        };
+        // four k-steps per group; the next group's loads are issued before
+        // the current group's MFMAs (register double buffering)
+        int kk = 0;
+        const int kend16 = kend & ~15;
+        if (kend16 > 0) {
+          T a0[MT], a1[MT], a2[MT], a3[MT];
+          kload(0, a0);
+          kload(4, a1);
+          kload(8, a2);
+          kload(12, a3);
+          for (; kk < kend16; kk += 16) {
+            T n0[MT], n1[MT], n2[MT], n3[MT];
+            const bool more = kk + 16 < kend16;
+            if (more) {
+              kload(kk + 16, n0);
+              kload(kk + 20, n1);
+              kload(kk + 24, n2);
+              kload(kk + 28, n3);
+            }
+            kstep(kk, a0);
+            kstep(kk + 4, a1);
+            kstep(kk + 8, a2);
+            kstep(kk + 12, a3);
+            if (more) {
+#pragma unroll
+              for (int t = 0; t < MT; ++t) {
+                a0[t] = n0[t];
+                a1[t] = n1[t];
+                a2[t] = n2[t];
+                a3[t] = n3[t];
+              }
+            }
+          }
+        }
+        for (; kk < kend; kk += 4) {
+          T a0[MT];
+          kload(kk, a0);
+          kstep(kk, a0);
         }
       }
     }
@@ -429,9 +527,13 @@ __global__ __launch_bounds__(256) void k_gemv_update(
 }
 
 // ------------------------------------------------------------- dispatch
+// About two workgroups per CU (256 CUs): one full wave of workgroups, few
+// enough partials that their reduction stays cheap.
+constexpr int kTargetGroups = 512;
+
 int pick_chunks(int ntiles, int64_t nbatches, int64_t per_chunk,
                 const Partials& P) {
-  int64_t target = (1024 + ntiles - 1) / ntiles;
+  int64_t target = (kTargetGroups + ntiles - 1) / ntiles;
   int64_t maxc = nbatches / 4;  // at least one batch per wavefront
   if (target > maxc) target = maxc;
   int64_t capc = per_chunk > 0 ? P.cap / per_chunk : target;
@@ -462,7 +564,7 @@ void gemm_tn(const T* A, int64_t lda, int ma, const T* B, int64_t ldb,
   if (ma <= 0 || nb <= 0) return;
   const int mt_all = (ma + 15) / 16, nt_all = (nb + 15) / 16;
   int NT = nt_all <= 1 ? 1 : (nt_all <= 2 ? 2 : 4);
-  const int mt_cap = sizeof(T) == 8 ? (NT == 4 ? 2 : 4) : (NT == 4 ? 4 : 8);
+  const int mt_cap = sizeof(T) == 8 ? (NT == 4 ? 2 : 8) : 4;
   int MT = 1;
   while (MT < mt_all && MT < mt_cap) MT *= 2;
   const int tiles_n = (nt_all + NT - 1) / NT;
@@ -481,11 +583,7 @@ void gemm_tn(const T* A, int64_t lda, int ma, const T* B, int64_t ldb,
   SGM_GT(1, 4) SGM_GT(2, 4) SGM_GT(4, 4)
   { throw Error{SGM_EINVAL, "gemm_tn: no kernel for this shape"}; }
 #undef SGM_GT
-  const int64_t ne = (int64_t)ma * nb;
-  hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)ceil_div(ne, 256)),
-                     dim3(256), 0, st, P.buf, (int64_t)chunks, ma, nb, C, ldc,
-                     0);
-  SGM_CHECK_LAUNCH();
+  launch_reduce(P.buf, chunks, ma, nb, C, ldc, 0, st);
 }
 
 namespace {
@@ -509,7 +607,7 @@ void launch_update(const T* A, int64_t lda, int ka, T* B, int64_t ldb,
   }
   const int64_t rows_per_block = 16 * MT * (kBlock / kWave);
   const int64_t nblocks = ceil_div(nrows, rows_per_block);
-  int64_t grid = nblocks < 1024 ? nblocks : 1024;
+  int64_t grid = nblocks < kTargetGroups ? nblocks : kTargetGroups;
   if (grid < 1) grid = 1;
   if (GRAM && grid * nc * nc > P.cap) {
     grid = P.cap / ((int64_t)nc * nc);
@@ -519,12 +617,7 @@ void launch_update(const T* A, int64_t lda, int ka, T* B, int64_t ldb,
                      dim3(kBlock), lds, st, A, lda, ka, B, ldb, nc, M, ldm,
                      ncount, nrows, kc, GRAM ? P.buf : (double*)nullptr);
   SGM_CHECK_LAUNCH();
-  if (GRAM) {
-    const int64_t ne = (int64_t)nc * nc;
-    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)ceil_div(ne, 256)),
-                       dim3(256), 0, st, P.buf, grid, nc, nc, G, ldg, 1);
-    SGM_CHECK_LAUNCH();
-  }
+  if (GRAM) launch_reduce(P.buf, grid, nc, nc, G, ldg, 1, st);
 }
 
 }  // namespace

@@ -185,16 +185,21 @@ def test_E1_monomial_step_size_six():
 
 @pytest.mark.slow
 def test_E2_laplace_monomial_step_size_six():
-    """P7b, Test 2: 2D Laplace 400^2, m = 100, monomial => s = 6 (one cycle
-    is enough to see the adapted size; the paper runs 5 restarts)."""
+    """P7b, Test 2: 2D Laplace 400^2, m = 100, monomial, s0 = 10 => every
+    block of the first cycle that the end of the cycle does not cut short
+    keeps s = 6 (one cycle is enough to see it; the paper runs 5 restarts).
+    The paper does not give b; a seeded N(0,1) vector is used.  (b = ones
+    is a poor stand-in: A 1 vanishes away from the boundary, which changes
+    the first block.)"""
     g = golden("paper_stability_results.json")["E2"]
     A = W.laplace_2d(400)
-    b = np.ones(A.n)
+    b = W.rhs(A.n, 1)
+    m = 100
     r = o.solve(csr(A), b, opts=o.Options(
-        s_max=10, restart=100, max_restarts=0, tol=1e-300, basis="monomial",
+        s_max=10, restart=m, max_restarts=0, tol=1e-300, basis="monomial",
         omega=1e7))
-    full = [p for (_, i, se, _, p) in r.blocks if se == 10]
-    assert full and all(p == g["adapted_s"] for p in full)
+    ps = [p for (_, i, _, _, p) in r.blocks if i + g["adapted_s"] <= m]
+    assert len(ps) >= 15 and all(p == g["adapted_s"] for p in ps)
 
 
 def test_E3_scaled_newton_single_block():
