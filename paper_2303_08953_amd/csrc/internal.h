@@ -43,6 +43,62 @@ const char* last_error();
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// ------------------------------------------------------------------ layout
+// Layout of a tall block of vectors (the Krylov basis Q).  Element (r, c)
+// sits at base + (r >> plog) * pstride + c * cstride + (r & pmask):
+//  - row panels (the solver's layout): 64-row panels, each holding the 64
+//    rows of every column contiguously (plog = 6, cstride = 64,
+//    pstride = 64 * ncols).  A kernel streaming many columns then reads a
+//    few contiguous regions instead of one far-apart stream per column,
+//    which keeps the memory system near its streaming bandwidth;
+//  - column-major with leading dimension ld (one panel: plog = 62,
+//    pstride = 0, cstride = ld), used by the step-level entry points.
+// Rows are processed in aligned groups of 16 that never straddle a panel.
+constexpr int kPanel = 64;
+template <typename T>
+struct QView {
+  T* base = nullptr;
+  int64_t pstride = 0;
+  int64_t cstride = 0;
+  int plog = 62;
+  __host__ __device__ __forceinline__ int64_t row_off(int64_t r) const {
+    return (r >> plog) * pstride + (r & ((int64_t(1) << plog) - 1));
+  }
+  __host__ __device__ __forceinline__ T* at(int64_t r, int64_t c) const {
+    return base + row_off(r) + c * cstride;
+  }
+  __host__ __device__ __forceinline__ T* col(int64_t c) const {
+    return base + c * cstride;
+  }
+  template <typename U>
+  __host__ __device__ QView<U> as() const {
+    QView<U> v;
+    v.base = base;
+    v.pstride = pstride;
+    v.cstride = cstride;
+    v.plog = plog;
+    return v;
+  }
+};
+template <typename T>
+inline QView<T> panel_view(T* base, int ncols) {
+  QView<T> v;
+  v.base = base;
+  v.pstride = (int64_t)kPanel * ncols;
+  v.cstride = kPanel;
+  v.plog = 6;
+  return v;
+}
+template <typename T>
+inline QView<T> colmajor_view(T* base, int64_t ld) {
+  QView<T> v;
+  v.base = base;
+  v.pstride = 0;
+  v.cstride = ld;
+  v.plog = 62;
+  return v;
+}
+
 // ------------------------------------------------------------------ matrix
 // SELL-C sparse layout with C = 64 (one wavefront per slice of 64 rows).
 // Slice s covers rows [64 s, 64 s + 64); its entries sit at
@@ -96,8 +152,8 @@ void spmv_plain(const Sell& S, const T* val, const T* x, T* y,
 // y = ((A x) - theta x - delta xprev) / gamma with (theta, gamma, delta) =
 // rec[3 j .. 3 j + 2] read on the device.
 template <typename T>
-void spmv_mpk(const Sell& S, const T* val, const T* x, const T* xprev, T* y,
-              const double* rec, int j, hipStream_t st);
+void spmv_mpk(const Sell& S, const T* val, QView<T> Q, int jx, int jprev,
+              int jy, const double* rec, int j, hipStream_t st);
 // r = b - A x (float64) and per-block partial sums of r^2 into part[];
 // returns the number of partials written.
 int64_t spmv_resid(const Sell& S, const double* val, const double* x,
@@ -107,13 +163,14 @@ int64_t resid_partials(const Sell& S);
 // ------------------------------------------------------------------ vectors
 // out[0] = sqrt(sum part[0..np)) (deterministic order).
 void reduce_norm(const double* part, int64_t np, double* out, hipStream_t st);
-// q = (T)(r / *beta) for rows < n, zero for rows n..ld.
+// column c of Q = (T)(r / *beta) for rows < n, zero for rows n..ld-1.
 template <typename T>
-void scale_into(const double* r, const double* beta, T* q, int64_t n,
-                int64_t ld, hipStream_t st);
-// zero rows n..ld-1 of columns [0, ncols) of a column-major matrix
+void scale_into(const double* r, const double* beta, QView<T> Q, int c,
+                int64_t n, int64_t ld, hipStream_t st);
+// zero rows n..ld-1 of columns [0, ncols) of Q
 template <typename T>
-void zero_pad_rows(T* Q, int64_t n, int64_t ld, int ncols, hipStream_t st);
+void zero_pad_rows(QView<T> Q, int64_t n, int64_t ld, int ncols,
+                   hipStream_t st);
 void jacobi_values(const Matrix& M, const Sell& S, double* v64, float* v32,
                    hipStream_t st);
 void vec_scale_div(double* x, const double* d, int64_t n, bool divide,
@@ -130,34 +187,33 @@ struct Partials {
   int64_t cap = 0;  // doubles
 };
 
-// C(ma x nb, ld ldc, float64) = A(:, 0:ma)^T B(:, 0:nb) over rows [0, nrows).
-// ncount (device, may be NULL) masks B's columns: only min(nb, *ncount) are
-// used (the rest of C is written as zero).
+// C(ma x nb, ld ldc, float64) = Q(:, a0:a0+ma)^T Q(:, b0:b0+nb) over rows
+// [0, nrows).  ncount (device, may be NULL) masks the B columns: only
+// min(nb, *ncount) are used (the rest of C is written as zero).
 template <typename T>
-void gemm_tn(const T* A, int64_t lda, int ma, const T* B, int64_t ldb,
-             int nb, const int* ncount, int64_t nrows, double* C, int ldc,
+void gemm_tn(QView<const T> Q, int a0, int ma, int b0, int nb,
+             const int* ncount, int64_t nrows, double* C, int ldc,
              Partials& P, hipStream_t st);
 
-// B(:, 0:nc) -= A(:, 0:ka) M(0:ka, 0:nc) (M float64, column-major, ld ldm)
-// and, when G is not NULL, G(nc x nc, ld ldg) = B^T B after the update.
-// ncount (device, may be NULL) limits nc to min(nc, *ncount).
+// Q(:, b0:b0+nc) -= Q(:, a0:a0+ka) M(0:ka, 0:nc) (M float64, column-major,
+// ld ldm) and, when G is not NULL, G(nc x nc, ld ldg) = the Gram matrix of
+// the updated columns.  ncount (device, may be NULL) limits nc.
 template <typename T>
-void update_gram(const T* A, int64_t lda, int ka, T* B, int64_t ldb, int nc,
-                 const double* M, int ldm, const int* ncount, int64_t nrows,
-                 double* G, int ldg, Partials& P, hipStream_t st);
+void update_gram(QView<T> Q, int a0, int ka, int b0, int nc, const double* M,
+                 int ldm, const int* ncount, int64_t nrows, double* G,
+                 int ldg, Partials& P, hipStream_t st);
 
-// B(:, 0:p) = B(:, 0:p) Rinv(0:p, 0:p) in place (Rinv upper triangular,
-// float64, ld ldr), p = min(s, *pcount).
+// Q(:, b0:b0+p) = Q(:, b0:b0+p) Rinv(0:p, 0:p) in place (Rinv upper
+// triangular, float64, ld ldr), p = min(s, *pcount).
 template <typename T>
-void trsm_inv(T* B, int64_t ldb, int s, const double* Rinv, int ldr,
+void trsm_inv(QView<T> Q, int b0, int s, const double* Rinv, int ldr,
               const int* pcount, int64_t nrows, hipStream_t st);
 
 // x(0:n) += scale * Q(:, 0:k) y(0:k), x float64, Q float64/float32,
-// k read from kdev, scale read from sdev (NULL = 1).
+// scale read from sdev (NULL = 1).
 template <typename T>
-void gemv_update(const T* Q, int64_t ldq, const double* y, const int* kdev,
-                 int kmax, const double* sdev, double* x, int64_t n,
-                 hipStream_t st);
+void gemv_update(QView<const T> Q, const double* y, int k,
+                 const double* sdev, double* x, int64_t n, hipStream_t st);
 
 // ------------------------------------------------------------------ small FP64
 // Control block shared by the single-workgroup kernels of one block.

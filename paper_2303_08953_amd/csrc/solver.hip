@@ -142,27 +142,27 @@ double ms_since(Clock::time_point t) {
 // sizes stay on the device (ctrl[C_P1], ctrl[C_P2]); later kernels read
 // them, so the sequence needs no host synchronisation.
 template <typename T>
-void orth_block(T* Q, int64_t ld, int64_t nrows, int nb, int s, double omega,
+void orth_block(QView<T> Q, int64_t nrows, int nb, int s, double omega,
                 Work& w, hipStream_t st, bool combine = true) {
-  T* V = Q + (int64_t)nb * ld;
+  const QView<const T> Qc = Q.template as<const T>();
   int* p1 = w.ctrl + C_P1;
   int* p2 = w.ctrl + C_P2;
   // first BCGS: W = Q^T V; V -= Q W; G = V^T V
-  gemm_tn<T>(Q, ld, nb, V, ld, s, nullptr, nrows, w.W, w.ldw, w.P, st);
-  update_gram<T>(Q, ld, nb, V, ld, s, w.W, w.ldw, nullptr, nrows, w.G, w.lds,
+  gemm_tn<T>(Qc, 0, nb, nb, s, nullptr, nrows, w.W, w.ldw, w.P, st);
+  update_gram<T>(Q, 0, nb, nb, s, w.W, w.ldw, nullptr, nrows, w.G, w.lds,
                  w.P, st);
   // first partial CholQR: p1, Z; V(:, 0:p1) = V Z^{-1}
   pchol_ice(w.G, w.lds, s, nullptr, omega, w.Z, w.Zinv, w.lds, p1,
             w.pchol_scr, st);
-  trsm_inv<T>(V, ld, s, w.Zinv, w.lds, p1, nrows, st);
+  trsm_inv<T>(Q, nb, s, w.Zinv, w.lds, p1, nrows, st);
   // second BCGS on the p1 accepted columns
-  gemm_tn<T>(Q, ld, nb, V, ld, s, p1, nrows, w.R2, w.ldw, w.P, st);
-  update_gram<T>(Q, ld, nb, V, ld, s, w.R2, w.ldw, p1, nrows, w.G2, w.lds,
-                 w.P, st);
+  gemm_tn<T>(Qc, 0, nb, nb, s, p1, nrows, w.R2, w.ldw, w.P, st);
+  update_gram<T>(Q, 0, nb, nb, s, w.R2, w.ldw, p1, nrows, w.G2, w.lds, w.P,
+                 st);
   // second partial CholQR: p2, Zt; V(:, 0:p2) = V Zt^{-1}
   pchol_ice(w.G2, w.lds, s, p1, omega, w.Zt, w.Ztinv, w.lds, p2, w.pchol_scr,
             st);
-  trsm_inv<T>(V, ld, s, w.Ztinv, w.lds, p2, nrows, st);
+  trsm_inv<T>(Q, nb, s, w.Ztinv, w.lds, p2, nrows, st);
   if (combine)
     combine_r(w.W, w.ldw, w.R2, w.ldw, w.Z, w.Zt, w.lds, nb, w.ctrl, w.Rtop,
               w.ldw, w.Rkk, w.lds, st);
@@ -221,8 +221,8 @@ struct Engine {
     for (auto& e : ev) (void)hipEventDestroy(e);
   }
 
-  T* Q() { return static_cast<T*>(w.Q); }
-  T* col(int j) { return Q() + (int64_t)j * ld; }
+  // the basis Q(:, 0 : m+1) in 64-row panels
+  QView<T> Q() const { return panel_view<T>(static_cast<T*>(w.Q), m + 2); }
 
   void set_monomial() {
     const double mono[3] = {0.0, 1.0, 0.0};
@@ -305,11 +305,11 @@ struct Engine {
     for (int j = 0; j < s_eff; ++j) {
       const int q = j % nrec;
       const double delta = mono ? 0.0 : sh.rec[3 * q + 2];
-      const T* xprev = (j >= 1 && delta != 0.0) ? col(nb - 2 + j) : nullptr;
-      spmv_mpk<T>(S, vals, col(nb - 1 + j), xprev, col(nb + j), rec, q, st);
+      const int jprev = (j >= 1 && delta != 0.0) ? nb - 2 + j : -1;
+      spmv_mpk<T>(S, vals, Q(), nb - 1 + j, jprev, nb + j, rec, q, st);
     }
     SGM_HIP(hipEventRecord(ev[1], st));
-    orth_block<T>(Q(), ld, ld, nb, s_eff, omega, w, st, false);
+    orth_block<T>(Q(), ld, nb, s_eff, omega, w, st, false);
     SGM_HIP(hipEventRecord(ev[2], st));
     block_tail(w.W, w.R2, w.ldw, w.Z, w.Zt, w.Zinv, w.Ztinv, w.lds, nb,
                w.ctrl, nullptr, nullptr, w.Hraw, w.Hr, w.ldh, w.cs, w.sn, w.g,
@@ -422,7 +422,8 @@ void run_solve(Handle* h, const double* b, const double* x0, double* x,
     SGM_HIP(hipMemcpyAsync(x, x0, sizeof(double) * n, hipMemcpyDeviceToDevice,
                            st));
   if (jac) vec_scale_div(x, A.diag, n, false, st);
-  zero_pad_rows<T>(static_cast<T*>(w.Q), n, w.ld, o.restart + 2, st);
+  zero_pad_rows<T>(panel_view<T>(static_cast<T*>(w.Q), o.restart + 2), n,
+                   w.ld, o.restart + 2, st);
   const double one = 1.0;
   SGM_HIP(hipMemcpyAsync(w.scal + 2, &one, sizeof(double),
                          hipMemcpyHostToDevice, st));
@@ -477,14 +478,15 @@ void run_solve(Handle* h, const double* b, const double* x0, double* x,
   };
   if (!f32) {
     if (!E.sh.known && !o.ritz_reuse) {
-      scale_into<T>(w.r, w.scal + 1, E.col(0), n, w.ld, st);
+      scale_into<T>(w.r, w.scal + 1, E.Q(), 0, n, w.ld, st);
       E.cycle(w.scal + 1, w.scal + 0, o.tol, true, 1.0, nullptr);
     }
     for (;;) {
-      scale_into<T>(w.r, w.scal + 1, E.col(0), n, w.ld, st);
+      scale_into<T>(w.r, w.scal + 1, E.Q(), 0, n, w.ld, st);
       const int k = E.cycle(w.scal + 1, w.scal + 0, o.tol, false, 1.0, nullptr);
       auto tc = Clock::now();
-      if (k > 0) gemv_update<T>(E.Q(), w.ld, w.y, nullptr, k, nullptr, x, n, st);
+      gemv_update<T>(E.Q().template as<const T>(), w.y, k, nullptr, x, n,
+                     st);
       R.t[5] += ms_since(tc);
       R.iters += k;
       beta = true_residual();
@@ -504,19 +506,19 @@ void run_solve(Handle* h, const double* b, const double* x0, double* x,
     // float32 inner cycles inside float64 iterative refinement
     auto tir = Clock::now();
     if (!E.sh.known && !o.ritz_reuse) {
-      scale_into<T>(w.r, w.scal + 1, E.col(0), n, w.ld, st);
+      scale_into<T>(w.r, w.scal + 1, E.Q(), 0, n, w.ld, st);
       E.cycle(w.scal + 2, w.scal + 2, o.inner_tol, true, 1.0, nullptr);
     }
     R.rel_true = 1.0;
     while (R.outer < o.max_outer) {
-      scale_into<T>(w.r, w.scal + 1, E.col(0), n, w.ld, st);
+      scale_into<T>(w.r, w.scal + 1, E.Q(), 0, n, w.ld, st);
       const double scale = beta / beta0;
       const int k =
           E.cycle(w.scal + 2, w.scal + 2, o.inner_tol, false, scale, nullptr);
       R.outer += 1;
       R.iters += k;
-      if (k > 0)
-        gemv_update<T>(E.Q(), w.ld, w.y, nullptr, k, w.scal + 1, x, n, st);
+      gemv_update<T>(E.Q().template as<const T>(), w.y, k, w.scal + 1, x, n,
+                     st);
       beta = true_residual();
       R.rel_true = beta / beta0;
       if (!std::isfinite(R.rel_true)) {
@@ -841,17 +843,15 @@ sgm_status sgm_mpk(sgm_matrix A, int transpose, sgm_precision precision,
   hipStream_t st = as_stream(stream);
   for (int j = 0; j < s; ++j) {
     const int q = j % n_rec;
-    if (precision == SGM_FP64) {
-      double* B = static_cast<double*>(Q);
-      spmv_mpk<double>(S, S.val64, B + (int64_t)(c + j) * ldq,
-                       j >= 1 ? B + (int64_t)(c + j - 1) * ldq : nullptr,
-                       B + (int64_t)(c + j + 1) * ldq, records, q, st);
-    } else {
-      float* B = static_cast<float*>(Q);
-      spmv_mpk<float>(S, S.val32, B + (int64_t)(c + j) * ldq,
-                      j >= 1 ? B + (int64_t)(c + j - 1) * ldq : nullptr,
-                      B + (int64_t)(c + j + 1) * ldq, records, q, st);
-    }
+    const int jprev = j >= 1 ? c + j - 1 : -1;
+    if (precision == SGM_FP64)
+      spmv_mpk<double>(S, S.val64,
+                       colmajor_view<double>(static_cast<double*>(Q), ldq),
+                       c + j, jprev, c + j + 1, records, q, st);
+    else
+      spmv_mpk<float>(S, S.val32,
+                      colmajor_view<float>(static_cast<float*>(Q), ldq),
+                      c + j, jprev, c + j + 1, records, q, st);
   }
   return SGM_OK;
   SGM_API_END
@@ -889,9 +889,11 @@ sgm_status sgm_block_orth(sgm_precision precision, int64_t n_rows, void* Q,
   const bool f32 = precision == SGM_FP32_IR;
   const double om = omega > 0 ? omega : default_omega(f32);
   if (f32)
-    orth_block<float>(static_cast<float*>(Q), ldq, ldq, i, s, om, w, st);
+    orth_block<float>(colmajor_view<float>(static_cast<float*>(Q), ldq), ldq,
+                      i, s, om, w, st);
   else
-    orth_block<double>(static_cast<double*>(Q), ldq, ldq, i, s, om, w, st);
+    orth_block<double>(colmajor_view<double>(static_cast<double*>(Q), ldq),
+                       ldq, i, s, om, w, st);
   int ctrl[C_NCTRL];
   SGM_HIP(hipMemcpyAsync(ctrl, w.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost,
                          st));

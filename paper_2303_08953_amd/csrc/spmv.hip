@@ -10,10 +10,13 @@ namespace {
 constexpr int kSpmvBlock = 256;                    // 4 wavefronts
 constexpr int kSlicesPerBlock = kSpmvBlock / kWave;
 
+// x, xprev and y are columns of a block of vectors with layout XV (row r of
+// a column at column base + XV.row_off(r)); the plain and residual
+// epilogues use contiguous vectors (column-major view).
 template <typename T, int EPI>
 __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
     const int64_t* __restrict__ ptr, const int32_t* __restrict__ width,
-    const int32_t* __restrict__ col, const T* __restrict__ val,
+    const int32_t* __restrict__ col, const T* __restrict__ val, QView<T> XV,
     const T* __restrict__ x, const T* __restrict__ xprev, T* __restrict__ y,
     const double* __restrict__ b, double* __restrict__ part, int64_t n,
     int64_t nslices, const double* __restrict__ rec, int j) {
@@ -31,25 +34,26 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
                     c3 = col[e + 3 * kSlice];
       const T v0 = val[e], v1 = val[e + kSlice], v2 = val[e + 2 * kSlice],
               v3 = val[e + 3 * kSlice];
-      sum += v0 * x[c0];
-      sum += v1 * x[c1];
-      sum += v2 * x[c2];
-      sum += v3 * x[c3];
+      sum += v0 * x[XV.row_off(c0)];
+      sum += v1 * x[XV.row_off(c1)];
+      sum += v2 * x[XV.row_off(c2)];
+      sum += v3 * x[XV.row_off(c3)];
     }
     for (; k < w; ++k) {
       const int64_t e = base + (int64_t)k * kSlice;
-      sum += val[e] * x[col[e]];
+      sum += val[e] * x[XV.row_off(col[e])];
     }
   }
   if constexpr (EPI == EPI_PLAIN) {
     if (r < n) y[r] = sum;
   } else if constexpr (EPI == EPI_MPK) {
     if (r < n) {
+      const int64_t ro = XV.row_off(r);
       const T theta = (T)rec[3 * j], gamma = (T)rec[3 * j + 1],
               delta = (T)rec[3 * j + 2];
-      T v = sum - theta * x[r];
-      if (xprev != nullptr) v = v - delta * xprev[r];
-      y[r] = v / gamma;
+      T v = sum - theta * x[ro];
+      if (xprev != nullptr) v = v - delta * xprev[ro];
+      y[ro] = v / gamma;
     }
   } else {  // EPI_RESID (float64): r = b - A x, partial sums of r^2
     double rr = 0.0;
@@ -90,20 +94,20 @@ __global__ __launch_bounds__(1024) void k_reduce_norm(const double* part,
 }
 
 template <typename T>
-__global__ void k_scale_into(const double* r, const double* beta, T* q,
-                             int64_t n, int64_t ld) {
+__global__ void k_scale_into(const double* r, const double* beta, QView<T> Q,
+                             int c, int64_t n, int64_t ld) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= ld) return;
-  q[i] = i < n ? (T)(r[i] / beta[0]) : (T)0;
+  *Q.at(i, c) = i < n ? (T)(r[i] / beta[0]) : (T)0;
 }
 
 template <typename T>
-__global__ void k_zero_pad(T* Q, int64_t n, int64_t ld, int ncols) {
+__global__ void k_zero_pad(QView<T> Q, int64_t n, int64_t ld, int ncols) {
   int64_t pad = ld - n;
   int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t >= pad * ncols) return;
   int64_t c = t / pad, r = n + t % pad;
-  Q[c * ld + r] = (T)0;
+  *Q.at(r, c) = (T)0;
 }
 
 __global__ void k_jacobi_values(const int64_t* src, const int32_t* col,
@@ -152,19 +156,21 @@ template <typename T>
 void spmv_plain(const Sell& S, const T* val, const T* x, T* y,
                 hipStream_t st) {
   hipLaunchKernelGGL((k_spmv<T, EPI_PLAIN>), dim3(spmv_grid(S)),
-                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, S.col, val, x,
-                     (const T*)nullptr, y, (const double*)nullptr,
-                     (double*)nullptr, S.n, S.nslices,
+                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, S.col, val,
+                     colmajor_view<T>(nullptr, 0), x, (const T*)nullptr, y,
+                     (const double*)nullptr, (double*)nullptr, S.n, S.nslices,
                      (const double*)nullptr, 0);
   SGM_CHECK_LAUNCH();
 }
 
 template <typename T>
-void spmv_mpk(const Sell& S, const T* val, const T* x, const T* xprev, T* y,
-              const double* rec, int j, hipStream_t st) {
+void spmv_mpk(const Sell& S, const T* val, QView<T> Q, int jx, int jprev,
+              int jy, const double* rec, int j, hipStream_t st) {
   hipLaunchKernelGGL((k_spmv<T, EPI_MPK>), dim3(spmv_grid(S)),
-                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, S.col, val, x,
-                     xprev, y, (const double*)nullptr, (double*)nullptr, S.n,
+                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, S.col, val, Q,
+                     (const T*)Q.col(jx),
+                     jprev >= 0 ? (const T*)Q.col(jprev) : (const T*)nullptr,
+                     Q.col(jy), (const double*)nullptr, (double*)nullptr, S.n,
                      S.nslices, rec, j);
   SGM_CHECK_LAUNCH();
 }
@@ -174,7 +180,8 @@ int64_t resid_partials(const Sell& S) { return spmv_grid(S); }
 int64_t spmv_resid(const Sell& S, const double* val, const double* x,
                    const double* b, double* r, double* part, hipStream_t st) {
   hipLaunchKernelGGL((k_spmv<double, EPI_RESID>), dim3(spmv_grid(S)),
-                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, S.col, val, x,
+                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, S.col, val,
+                     colmajor_view<double>(nullptr, 0), x,
                      (const double*)nullptr, r, b, part, S.n, S.nslices,
                      (const double*)nullptr, 0);
   SGM_CHECK_LAUNCH();
@@ -185,12 +192,10 @@ template void spmv_plain<double>(const Sell&, const double*, const double*,
                                  double*, hipStream_t);
 template void spmv_plain<float>(const Sell&, const float*, const float*,
                                 float*, hipStream_t);
-template void spmv_mpk<double>(const Sell&, const double*, const double*,
-                               const double*, double*, const double*, int,
-                               hipStream_t);
-template void spmv_mpk<float>(const Sell&, const float*, const float*,
-                              const float*, float*, const double*, int,
-                              hipStream_t);
+template void spmv_mpk<double>(const Sell&, const double*, QView<double>, int,
+                               int, int, const double*, int, hipStream_t);
+template void spmv_mpk<float>(const Sell&, const float*, QView<float>, int,
+                              int, int, const double*, int, hipStream_t);
 
 void reduce_norm(const double* part, int64_t np, double* out,
                  hipStream_t st) {
@@ -200,27 +205,28 @@ void reduce_norm(const double* part, int64_t np, double* out,
 }
 
 template <typename T>
-void scale_into(const double* r, const double* beta, T* q, int64_t n,
-                int64_t ld, hipStream_t st) {
+void scale_into(const double* r, const double* beta, QView<T> Q, int c,
+                int64_t n, int64_t ld, hipStream_t st) {
   hipLaunchKernelGGL(k_scale_into<T>, dim3(g1(ld)), dim3(256), 0, st, r,
-                     beta, q, n, ld);
+                     beta, Q, c, n, ld);
   SGM_CHECK_LAUNCH();
 }
-template void scale_into<double>(const double*, const double*, double*,
-                                 int64_t, int64_t, hipStream_t);
-template void scale_into<float>(const double*, const double*, float*,
-                                int64_t, int64_t, hipStream_t);
+template void scale_into<double>(const double*, const double*, QView<double>,
+                                 int, int64_t, int64_t, hipStream_t);
+template void scale_into<float>(const double*, const double*, QView<float>,
+                                int, int64_t, int64_t, hipStream_t);
 
 template <typename T>
-void zero_pad_rows(T* Q, int64_t n, int64_t ld, int ncols, hipStream_t st) {
+void zero_pad_rows(QView<T> Q, int64_t n, int64_t ld, int ncols,
+                   hipStream_t st) {
   if (ld <= n || ncols <= 0) return;
   hipLaunchKernelGGL(k_zero_pad<T>, dim3(g1((ld - n) * ncols)), dim3(256), 0,
                      st, Q, n, ld, ncols);
   SGM_CHECK_LAUNCH();
 }
-template void zero_pad_rows<double>(double*, int64_t, int64_t, int,
+template void zero_pad_rows<double>(QView<double>, int64_t, int64_t, int,
                                     hipStream_t);
-template void zero_pad_rows<float>(float*, int64_t, int64_t, int,
+template void zero_pad_rows<float>(QView<float>, int64_t, int64_t, int,
                                    hipStream_t);
 
 void jacobi_values(const Matrix& M, const Sell& S, double* v64, float* v32,

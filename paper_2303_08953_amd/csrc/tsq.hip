@@ -105,18 +105,20 @@ __device__ __forceinline__ void store_rows(T* p, const T (&in)[MT]) {
 constexpr int kBlock = 256;  // 4 wavefronts per workgroup
 
 // ------------------------------------------------------------- A^T B
+// C = Q(:, a0:a0+ma)^T Q(:, b0:b0+nb) over 16-row batches of Q.
 // Grid: 1-D, chunks * ntiles workgroups (chunks a multiple of 8).  XCD-aware
 // decode: workgroup id -> (xcd = id % 8, slot = id / 8); the ntiles output
 // tiles of one row chunk get consecutive slots on the same XCD, so they run
-// together and share that XCD's L2 for the A and B rows they all read.
+// together and share that XCD's L2 for the rows they all read.
 // Each wavefront consumes 16-row batches; lane (g = l/16, c = l%16) loads
 // rows 4g..4g+3 of one column as a 4-vector, and MFMA step t pairs row
-// 4g + t of A with the same row of B.
+// 4g + t of A with the same row of B.  A 16-row batch never straddles a
+// row panel, so one row offset per batch serves every column.
 template <typename T, int MT, int NT>
 __global__ __launch_bounds__(kBlock) void k_gemm_tn(
-    const T* __restrict__ A, int64_t lda, int ma, const T* __restrict__ B,
-    int64_t ldb, int nb, const int* __restrict__ ncount, int64_t nbatches,
-    int tiles_n, int ntiles, int chunks, double* __restrict__ part) {
+    QView<const T> Q, int a0, int ma, int b0c, int nb,
+    const int* __restrict__ ncount, int64_t nbatches, int tiles_n, int ntiles,
+    int chunks, double* __restrict__ part) {
   typedef typename Vec4<T>::type V;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int g = lane / 16, c16 = lane % 16;
@@ -130,20 +132,17 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(
   const int64_t b0 = nbatches * chunk / chunks;
   const int64_t b1 = nbatches * (chunk + 1) / chunks;
 
-  const T* pa[MT];
-  const T* pb[NT];
-  bool va[MT], vb[NT];
+  // per-lane column offsets; a column past the end reads column a0 / b0c
+  int64_t oa[MT], ob[NT];
 #pragma unroll
   for (int i = 0; i < MT; ++i) {
     const int c = m0 + i * 16 + c16;
-    va[i] = c < ma;
-    pa[i] = A + (int64_t)(va[i] ? c : 0) * lda + 4 * g;
+    oa[i] = (int64_t)(a0 + (c < ma ? c : 0)) * Q.cstride + 4 * g;
   }
 #pragma unroll
   for (int i = 0; i < NT; ++i) {
     const int c = n0 + i * 16 + c16;
-    vb[i] = c < nbe;
-    pb[i] = B + (int64_t)(vb[i] ? c : 0) * ldb + 4 * g;
+    ob[i] = (int64_t)(b0c + (c < nbe ? c : 0)) * Q.cstride + 4 * g;
   }
   V acc[MT][NT];
 #pragma unroll
@@ -163,11 +162,11 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(
   // between a load and its MFMA, the compiler waits for the current batch
   // only while the next one is in flight.
   auto load = [&](int64_t bt, V (&a)[MT], V (&b)[NT]) {
-    const int64_t row = bt * 16;
+    const T* rb = Q.base + Q.row_off(bt * 16);
 #pragma unroll
-    for (int i = 0; i < MT; ++i) a[i] = *reinterpret_cast<const V*>(pa[i] + row);
+    for (int i = 0; i < MT; ++i) a[i] = *reinterpret_cast<const V*>(rb + oa[i]);
 #pragma unroll
-    for (int j = 0; j < NT; ++j) b[j] = *reinterpret_cast<const V*>(pb[j] + row);
+    for (int j = 0; j < NT; ++j) b[j] = *reinterpret_cast<const V*>(rb + ob[j]);
   };
   int64_t bt = b0 + wave;
   if (bt < b1) load(bt, af, bf);
@@ -285,18 +284,19 @@ void launch_reduce(const double* part, int64_t nchunks, int ma, int nb,
 // Tile row m of row-tile t is physical row r0 + MT*m + t, so a lane's A
 // operand for the MT row tiles is one contiguous MT-vector of a column, and
 // the MT results sharing a D index are contiguous rows too.
-// MODE_UPDATE: B(:, 0:nc) = B - A(:, 0:ka) M(0:ka, 0:nc), and (GRAM) the
-//              partial Gram B^T B of the updated rows.
+// With A = Q(:, a0:a0+ka) and B = Q(:, b0:b0+nc):
+// MODE_UPDATE: B(:, 0:nc) = B - A M(0:ka, 0:nc), and (GRAM) the partial
+//              Gram B^T B of the updated rows.
 // MODE_TRSM:   B(:, 0:p) = B(:, 0:p) M(0:p, 0:p) in place, M upper
 //              triangular (tiles below the diagonal are skipped).
+// A wavefront's 16*MT rows (16, 32 or 64, aligned) lie in one row panel.
 enum { MODE_UPDATE = 0, MODE_TRSM = 1 };
 
 template <typename T, int NT, int MT, int MODE, bool GRAM>
 __global__ __launch_bounds__(kBlock) void k_update(
-    const T* __restrict__ A, int64_t lda, int ka, T* __restrict__ B,
-    int64_t ldb, int nc, const double* __restrict__ M, int ldm,
-    const int* __restrict__ ncount, int64_t nrows, int kc,
-    double* __restrict__ part) {
+    QView<T> Q, int a0, int ka, int b0c, int nc,
+    const double* __restrict__ M, int ldm, const int* __restrict__ ncount,
+    int64_t nrows, int kc, double* __restrict__ part) {
   typedef typename Vec4<T>::type V;
   extern __shared__ char smem_raw[];
   T* Ms = reinterpret_cast<T*>(smem_raw);
@@ -338,6 +338,9 @@ __global__ __launch_bounds__(kBlock) void k_update(
   for (int64_t rb = blockIdx.x; rb < nblocks; rb += gridDim.x) {
     const int64_t r0 = rb * rows_per_block + wave * rows_per_wave;
     const bool active = r0 < nrows;
+    T* const rbase = Q.base + Q.row_off(r0);
+    T* const B = rbase + (int64_t)b0c * Q.cstride;
+    const int64_t cs = Q.cstride;
     V acc[MT][NT];
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
@@ -346,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_update(
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           T v[MT];
-          load_rows<T, MT>(B + (int64_t)c * ldb + r0 + MT * drow<T>(g, q), v);
+          load_rows<T, MT>(B + (int64_t)c * cs + MT * drow<T>(g, q), v);
 #pragma unroll
           for (int t = 0; t < MT; ++t) acc[t][j][q] = v[t];
         }
@@ -363,9 +366,9 @@ __global__ __launch_bounds__(kBlock) void k_update(
       }
       const int kend = min(kc, ka4 - k0);
       if (active) {
-        const T* src = MODE == MODE_TRSM ? (const T*)B : A;
-        const int64_t lds_ = MODE == MODE_TRSM ? ldb : lda;
-        const T* base = src + r0 + MT * c16;
+        const T* base = rbase +
+                        (int64_t)(MODE == MODE_TRSM ? b0c : a0) * cs +
+                        MT * c16;
         auto kstep = [&](int kk, const T (&a)[MT]) {
           const T* mrow = Ms + (kk + g) * W16 + c16;
 #pragma unroll
@@ -381,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_update(
         // outstanding loads
         auto kload = [&](int kk, T (&a)[MT]) {
           const int k = k0 + kk + g;
-          load_rows<T, MT>(base + (int64_t)(k < kae ? k : 0) * lds_, a);
+          load_rows<T, MT>(base + (int64_t)(k < kae ? k : 0) * cs, a);
         };
         // four k-steps per group; the next group's loads are issued before
         // the current group's MFMAs (register double buffering)
@@ -434,7 +437,7 @@ __global__ __launch_bounds__(kBlock) void k_update(
             T v[MT];
 #pragma unroll
             for (int t = 0; t < MT; ++t) v[t] = acc[t][j][q];
-            store_rows<T, MT>(B + (int64_t)c * ldb + r0 + MT * drow<T>(g, q), v);
+            store_rows<T, MT>(B + (int64_t)c * cs + MT * drow<T>(g, q), v);
           }
         }
       }
@@ -494,15 +497,15 @@ __global__ __launch_bounds__(kBlock) void k_update(
   }
 }
 
-// x(r) += scale * sum_j Q(r, j) y(j), j < k (float64 accumulation).
+// x(r) += scale * sum_j Q(r, j) y(j), j < k (float64 accumulation).  A
+// wavefront's 64 consecutive rows read 64 contiguous elements per column.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemv_update(
-    const T* __restrict__ Q, int64_t ldq, const double* __restrict__ y,
-    const int* __restrict__ kdev, int kmax, const double* __restrict__ sdev,
-    double* __restrict__ x, int64_t n) {
+    QView<const T> Q, const double* __restrict__ y, int k,
+    const double* __restrict__ sdev, double* __restrict__ x, int64_t n) {
   __shared__ double ys[1024];
-  const int k = kdev ? min(kmax, *kdev) : kmax;
   const double sc = sdev ? sdev[0] : 1.0;
+  const int64_t cs = Q.cstride;
   for (int base = 0; base < k; base += 1024) {
     __syncthreads();
     for (int j = threadIdx.x; j < 1024 && base + j < k; j += blockDim.x)
@@ -512,15 +515,15 @@ __global__ __launch_bounds__(256) void k_gemv_update(
          r += (int64_t)gridDim.x * blockDim.x) {
       double acc = 0.0;
       const int kk = min(1024, k - base);
-      const T* q = Q + (int64_t)base * ldq + r;
+      const T* q = Q.base + Q.row_off(r) + (int64_t)base * cs;
       int j = 0;
       for (; j + 4 <= kk; j += 4) {
-        acc += (double)q[(int64_t)j * ldq] * ys[j];
-        acc += (double)q[(int64_t)(j + 1) * ldq] * ys[j + 1];
-        acc += (double)q[(int64_t)(j + 2) * ldq] * ys[j + 2];
-        acc += (double)q[(int64_t)(j + 3) * ldq] * ys[j + 3];
+        acc += (double)q[(int64_t)j * cs] * ys[j];
+        acc += (double)q[(int64_t)(j + 1) * cs] * ys[j + 1];
+        acc += (double)q[(int64_t)(j + 2) * cs] * ys[j + 2];
+        acc += (double)q[(int64_t)(j + 3) * cs] * ys[j + 3];
       }
-      for (; j < kk; ++j) acc += (double)q[(int64_t)j * ldq] * ys[j];
+      for (; j < kk; ++j) acc += (double)q[(int64_t)j * cs] * ys[j];
       x[r] += sc * acc;
     }
   }
@@ -546,20 +549,20 @@ int pick_chunks(int ntiles, int64_t nbatches, int64_t per_chunk,
 }
 
 template <typename T, int MT, int NT>
-void launch_gemm_tn(const T* A, int64_t lda, int ma, const T* B, int64_t ldb,
-                    int nb, const int* ncount, int64_t nbatches, int tiles_n,
+void launch_gemm_tn(QView<const T> Q, int a0, int ma, int b0, int nb,
+                    const int* ncount, int64_t nbatches, int tiles_n,
                     int ntiles, int chunks, double* part, hipStream_t st) {
   hipLaunchKernelGGL((k_gemm_tn<T, MT, NT>), dim3(chunks * ntiles),
-                     dim3(kBlock), 0, st, A, lda, ma, B, ldb, nb, ncount,
-                     nbatches, tiles_n, ntiles, chunks, part);
+                     dim3(kBlock), 0, st, Q, a0, ma, b0, nb, ncount, nbatches,
+                     tiles_n, ntiles, chunks, part);
   SGM_CHECK_LAUNCH();
 }
 
 }  // namespace
 
 template <typename T>
-void gemm_tn(const T* A, int64_t lda, int ma, const T* B, int64_t ldb,
-             int nb, const int* ncount, int64_t nrows, double* C, int ldc,
+void gemm_tn(QView<const T> Q, int a0, int ma, int b0, int nb,
+             const int* ncount, int64_t nrows, double* C, int ldc,
              Partials& P, hipStream_t st) {
   if (ma <= 0 || nb <= 0) return;
   const int mt_all = (ma + 15) / 16, nt_all = (nb + 15) / 16;
@@ -575,8 +578,8 @@ void gemm_tn(const T* A, int64_t lda, int ma, const T* B, int64_t ldb,
       pick_chunks(ntiles, nbatches, (int64_t)ma * nb, P);
 #define SGM_GT(mt, nt)                                                      \
   if (MT == mt && NT == nt) {                                               \
-    launch_gemm_tn<T, mt, nt>(A, lda, ma, B, ldb, nb, ncount, nbatches,     \
-                              tiles_n, ntiles, chunks, P.buf, st);          \
+    launch_gemm_tn<T, mt, nt>(Q, a0, ma, b0, nb, ncount, nbatches, tiles_n, \
+                              ntiles, chunks, P.buf, st);                   \
   } else
   SGM_GT(1, 1) SGM_GT(2, 1) SGM_GT(4, 1) SGM_GT(8, 1)
   SGM_GT(1, 2) SGM_GT(2, 2) SGM_GT(4, 2) SGM_GT(8, 2)
@@ -591,10 +594,9 @@ namespace {
 constexpr int kLdsBudget = 64 * 1024;
 
 template <typename T, int NT, int MT, int MODE, bool GRAM>
-void launch_update(const T* A, int64_t lda, int ka, T* B, int64_t ldb,
-                   int nc, const double* M, int ldm, const int* ncount,
-                   int64_t nrows, double* G, int ldg, Partials& P,
-                   hipStream_t st) {
+void launch_update(QView<T> Q, int a0, int ka, int b0, int nc,
+                   const double* M, int ldm, const int* ncount, int64_t nrows,
+                   double* G, int ldg, Partials& P, hipStream_t st) {
   const int W16 = NT * 16;
   const int ka4 = (ka + 3) & ~3;
   int kc = kLdsBudget / (W16 * (int)sizeof(T));
@@ -614,8 +616,8 @@ void launch_update(const T* A, int64_t lda, int ka, T* B, int64_t ldb,
     if (grid < 1) throw Error{SGM_EINVAL, "partial scratch too small"};
   }
   hipLaunchKernelGGL((k_update<T, NT, MT, MODE, GRAM>), dim3((unsigned)grid),
-                     dim3(kBlock), lds, st, A, lda, ka, B, ldb, nc, M, ldm,
-                     ncount, nrows, kc, GRAM ? P.buf : (double*)nullptr);
+                     dim3(kBlock), lds, st, Q, a0, ka, b0, nc, M, ldm, ncount,
+                     nrows, kc, GRAM ? P.buf : (double*)nullptr);
   SGM_CHECK_LAUNCH();
   if (GRAM) launch_reduce(P.buf, grid, nc, nc, G, ldg, 1, st);
 }
@@ -623,9 +625,9 @@ void launch_update(const T* A, int64_t lda, int ka, T* B, int64_t ldb,
 }  // namespace
 
 template <typename T>
-void update_gram(const T* A, int64_t lda, int ka, T* B, int64_t ldb, int nc,
-                 const double* M, int ldm, const int* ncount, int64_t nrows,
-                 double* G, int ldg, Partials& P, hipStream_t st) {
+void update_gram(QView<T> Q, int a0, int ka, int b0, int nc, const double* M,
+                 int ldm, const int* ncount, int64_t nrows, double* G,
+                 int ldg, Partials& P, hipStream_t st) {
   if (nc <= 0) return;
   const int nt = (nc + 15) / 16;
   const bool fuse = G != nullptr && nt <= 4;
@@ -633,10 +635,10 @@ void update_gram(const T* A, int64_t lda, int ka, T* B, int64_t ldb, int nc,
   if (nt == NTv) {                                                            \
     if (fuse)                                                                 \
       launch_update<T, NTv, MTv, MODE_UPDATE, (NTv <= 4)>(                    \
-          A, lda, ka, B, ldb, nc, M, ldm, ncount, nrows, G, ldg, P, st);      \
+          Q, a0, ka, b0, nc, M, ldm, ncount, nrows, G, ldg, P, st);           \
     else                                                                      \
       launch_update<T, NTv, MTv, MODE_UPDATE, false>(                         \
-          A, lda, ka, B, ldb, nc, M, ldm, ncount, nrows, nullptr, 0, P, st);  \
+          Q, a0, ka, b0, nc, M, ldm, ncount, nrows, nullptr, 0, P, st);       \
   } else
   SGM_UP(1, 4) SGM_UP(2, 4) SGM_UP(3, 2) SGM_UP(4, 2) SGM_UP(5, 1)
   SGM_UP(6, 1) SGM_UP(7, 1) SGM_UP(8, 1) SGM_UP(9, 1) SGM_UP(10, 1)
@@ -645,11 +647,12 @@ void update_gram(const T* A, int64_t lda, int ka, T* B, int64_t ldb, int nc,
   { throw Error{SGM_EINVAL, "update: block wider than 256 columns"}; }
 #undef SGM_UP
   if (G != nullptr && !fuse)
-    gemm_tn<T>(B, ldb, nc, B, ldb, nc, ncount, nrows, G, ldg, P, st);
+    gemm_tn<T>(Q.template as<const T>(), b0, nc, b0, nc, ncount, nrows, G,
+               ldg, P, st);
 }
 
 template <typename T>
-void trsm_inv(T* B, int64_t ldb, int s, const double* Rinv, int ldr,
+void trsm_inv(QView<T> Q, int b0, int s, const double* Rinv, int ldr,
               const int* pcount, int64_t nrows, hipStream_t st) {
   if (s <= 0) return;
   Partials none;
@@ -657,8 +660,7 @@ void trsm_inv(T* B, int64_t ldb, int s, const double* Rinv, int ldr,
 #define SGM_TR(NTv, MTv)                                                      \
   if (nt == NTv) {                                                            \
     launch_update<T, NTv, MTv, MODE_TRSM, false>(                             \
-        nullptr, 0, s, B, ldb, s, Rinv, ldr, pcount, nrows, nullptr, 0, none, \
-        st);                                                                  \
+        Q, 0, s, b0, s, Rinv, ldr, pcount, nrows, nullptr, 0, none, st);      \
   } else
   SGM_TR(1, 4) SGM_TR(2, 4) SGM_TR(3, 2) SGM_TR(4, 2) SGM_TR(5, 1)
   SGM_TR(6, 1) SGM_TR(7, 1) SGM_TR(8, 1) SGM_TR(9, 1) SGM_TR(10, 1)
@@ -669,28 +671,26 @@ void trsm_inv(T* B, int64_t ldb, int s, const double* Rinv, int ldr,
 }
 
 template <typename T>
-void gemv_update(const T* Q, int64_t ldq, const double* y, const int* kdev,
-                 int kmax, const double* sdev, double* x, int64_t n,
-                 hipStream_t st) {
+void gemv_update(QView<const T> Q, const double* y, int k,
+                 const double* sdev, double* x, int64_t n, hipStream_t st) {
+  if (k <= 0) return;
   int64_t grid = ceil_div(n, 256);
   if (grid > 4096) grid = 4096;
   hipLaunchKernelGGL(k_gemv_update<T>, dim3((unsigned)grid), dim3(256), 0,
-                     st, Q, ldq, y, kdev, kmax, sdev, x, n);
+                     st, Q, y, k, sdev, x, n);
   SGM_CHECK_LAUNCH();
 }
 
 #define SGM_INST(T)                                                          \
-  template void gemm_tn<T>(const T*, int64_t, int, const T*, int64_t, int,   \
-                           const int*, int64_t, double*, int, Partials&,     \
-                           hipStream_t);                                     \
-  template void update_gram<T>(const T*, int64_t, int, T*, int64_t, int,     \
-                               const double*, int, const int*, int64_t,      \
-                               double*, int, Partials&, hipStream_t);        \
-  template void trsm_inv<T>(T*, int64_t, int, const double*, int,            \
+  template void gemm_tn<T>(QView<const T>, int, int, int, int, const int*,   \
+                           int64_t, double*, int, Partials&, hipStream_t);   \
+  template void update_gram<T>(QView<T>, int, int, int, int, const double*,  \
+                               int, const int*, int64_t, double*, int,       \
+                               Partials&, hipStream_t);                      \
+  template void trsm_inv<T>(QView<T>, int, int, const double*, int,          \
                             const int*, int64_t, hipStream_t);               \
-  template void gemv_update<T>(const T*, int64_t, const double*, const int*, \
-                               int, const double*, double*, int64_t,         \
-                               hipStream_t);
+  template void gemv_update<T>(QView<const T>, const double*, int,           \
+                               const double*, double*, int64_t, hipStream_t);
 SGM_INST(double)
 SGM_INST(float)
 #undef SGM_INST
