@@ -12,6 +12,13 @@ namespace {
 
 constexpr int kSmallBlock = 256;
 
+// Broadcast lane `lane`'s value of a double to the whole wavefront.
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
 // Largest eigenvalue of [[a, b], [b, c]] and a unit eigenvector (u, v).
 __device__ void top_eig_2x2(double a, double b, double c, double& lam,
                             double& u, double& v) {
@@ -28,107 +35,133 @@ __device__ void top_eig_2x2(double a, double b, double c, double& lam,
 }
 
 // Partial Cholesky (Alg. 3) of the leading s x s block of G, right-looking,
-// in LDS (row-major work copy; thread k % nthr owns column k).  After the
-// pivot of column j the incremental condition estimator takes its step.
-// The estimator keeps unit approximate singular vectors y (largest singular
-// value, |y^T R|) and d = R^{-T} x (smallest, 1/|d|); column j's update is
-// a 2x2 symmetric eigenproblem in (sin, cos) that needs a = y^T R(0:j, j)
-// and a2 = d^T R(0:j, j).  Both are kept as running sums for every later
-// column k: when row j of R appears, P_k <- s1 P_k + c1 R(j, k) and
-// Q_k <- s2 Q_k + d_j R(j, k), which is exactly y^T R(0:j+1, k) and
-// d^T R(0:j+1, k) after the update y <- [s1 y; c1], d <- [s2 d; d_j].  No
-// reductions are needed; the owner of column j broadcasts (P_j, Q_j).
+// in LDS (row-major work copy).  Thread k owns column k (s <= blockDim.x).
+// After the pivot of column j the incremental condition estimator takes its
+// step.  The estimator keeps unit approximate singular vectors y (largest
+// singular value, |y^T R|) and d = R^{-T} x (smallest, 1/|d|); column j's
+// update is a 2x2 symmetric eigenproblem in (sin, cos) that needs
+// a = y^T R(0:j, j) and a2 = d^T R(0:j, j).  Both are kept as running sums
+// for every later column k: when row j of R appears, P_k <- s1 P_k +
+// c1 R(j, k) and Q_k <- s2 Q_k + d_j R(j, k), which is exactly
+// y^T R(0:j+1, k) and d^T R(0:j+1, k) after the update y <- [s1 y; c1],
+// d <- [s2 d; d_j].  No reductions are needed: the owner of column j + 1
+// publishes (P, Q) for the next step.
+// Each step: (1) every thread evaluates the pivot and the estimator
+// (uniform), (2) the owners scale row j and publish it to rowj[], (3) all
+// threads apply the rank-1 trailing update, one element per lane: lane
+// (wave w, lane l) updates column j+1+l (+64 ...) at rows j+1+w, j+1+w+nw,
+// ... so row j's entries come from rowj[] as broadcasts.
 // The factorisation stops before a column whose pivot is not positive and
 // finite or whose estimate exceeds omega.  Outputs: p, R (p x p upper),
 // Rinv = R^{-1} (explicit, column-wise back substitution in LDS), both
 // column-major with leading dimension ldr.
-constexpr int kPcholLds = 144 * 1024 / 8;
-constexpr int kPcholCols = 4;  // columns per thread: s <= 4 * blockDim.x
+constexpr int kPcholLds = 140 * 1024 / 8;
+constexpr int kPcholMaxS = 256;
 
 // The body is instantiated twice: with the LDS array (every access then
 // compiles to a ds_* instruction) and with global scratch for large s.
 __device__ __forceinline__ void pchol_body(
-    double* Aw, double* bc, const double* __restrict__ G, int ldg, int s,
-    double omega, double* __restrict__ R, double* __restrict__ Rinv, int ldr,
-    int* p_out) {
+    double* Aw, double* rowj, double (*bc)[2], const double* __restrict__ G,
+    int ldg, int s, double omega, double* __restrict__ R,
+    double* __restrict__ Rinv, int ldr, int* p_out) {
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
+  const int lane = tid % kWave, wave = tid / kWave, nw = nthr / kWave;
   const int la = s > 0 ? s : 1;
   double* Ri = Aw + (size_t)s * s;
   for (int e = tid; e < s * s; e += nthr) {
     const int i = e % s, j = e / s;  // G symmetric: (i, j) -> row i, col j
     Aw[i * la + j] = G[(int64_t)j * ldg + i];
   }
-  double P[kPcholCols], Q[kPcholCols];
-#pragma unroll
-  for (int q = 0; q < kPcholCols; ++q) { P[q] = 0.0; Q[q] = 0.0; }
+  double P = 0.0, Q = 0.0;  // estimator sums of column tid
   double smax2 = 0.0, dn2 = 0.0;  // uniform estimator state
   int p = s;
   __syncthreads();
   for (int j = 0; j < s; ++j) {
-    const int owner = j % nthr, qj = j / nthr;
-    if (tid == owner) {
-      double pj = 0.0, qv = 0.0;
-#pragma unroll
-      for (int q = 0; q < kPcholCols; ++q)
-        if (q == qj) { pj = P[q]; qv = Q[q]; }
-      bc[0] = pj;
-      bc[1] = qv;
-    }
-    __syncthreads();
+    // (1) pivot and estimator, evaluated identically by every thread
     const double piv = Aw[j * la + j];
     if (!(piv > 0.0) || !isfinite(piv)) { p = j; break; }
     const double rjj = sqrt(piv);
+    const double rinv = 1.0 / rjj;
     double s1 = 0.0, c1 = 1.0, s2 = 0.0, c2 = 1.0, kappa = 1.0, a2 = 0.0;
     const double r2 = rjj * rjj;
     if (j == 0) {
       smax2 = r2;
-      dn2 = 1.0 / r2;
+      dn2 = rinv * rinv;
     } else {
-      const double a = bc[0];
-      a2 = bc[1];
-      double lam1, lam2;
-      top_eig_2x2(smax2 + a * a, a * rjj, r2, lam1, s1, c1);
-      top_eig_2x2(dn2 + (a2 / rjj) * (a2 / rjj), -a2 / r2, 1.0 / r2, lam2,
-                  s2, c2);
-      smax2 = lam1;
-      dn2 = lam2;
+      // the two 2x2 eigenproblems (largest and smallest singular value)
+      // run side by side: even lanes take the first, odd lanes the second
+      const double a = bc[j & 1][0];
+      a2 = bc[j & 1][1];
+      const bool second = lane & 1;
+      const double ar = a2 * rinv;
+      const double ea = second ? dn2 + ar * ar : smax2 + a * a;
+      const double eb = second ? -ar * rinv : a * rjj;
+      const double ec = second ? rinv * rinv : r2;
+      double lam, u, v;
+      top_eig_2x2(ea, eb, ec, lam, u, v);
+      smax2 = readlane_f64(lam, 0);
+      s1 = readlane_f64(u, 0);
+      c1 = readlane_f64(v, 0);
+      dn2 = readlane_f64(lam, 1);
+      s2 = readlane_f64(u, 1);
+      c2 = readlane_f64(v, 1);
       kappa = sqrt(smax2 * dn2);
     }
     if (!(kappa <= omega)) { p = j; break; }
-    const double dj = (c2 - s2 * a2) / rjj;
-    // row j of R and the running estimator sums of the owned columns
-#pragma unroll
-    for (int q = 0; q < kPcholCols; ++q) {
-      const int k = tid + q * nthr;
-      if (k > j && k < s) {
-        const double rjk = Aw[j * la + k] / rjj;
-        Aw[j * la + k] = rjk;
-        P[q] = s1 * P[q] + c1 * rjk;
-        Q[q] = s2 * Q[q] + dj * rjk;
+    const double dj = (c2 - s2 * a2) * rinv;
+    // (2) row j of R, the owners' running estimator sums, and (P, Q) of
+    // column j + 1 for the next step
+    if (tid > j && tid < s) {
+      const double rjk = Aw[j * la + tid] * rinv;
+      Aw[j * la + tid] = rjk;
+      rowj[tid] = rjk;
+      P = s1 * P + c1 * rjk;
+      Q = s2 * Q + dj * rjk;
+      if (tid == j + 1) {
+        bc[(j + 1) & 1][0] = P;
+        bc[(j + 1) & 1][1] = Q;
       }
     }
-    if (tid == owner) Aw[j * la + j] = rjj;
+    if (tid == j) Aw[j * la + j] = rjj;
     __syncthreads();
-    // trailing update of the owned columns: A(l, k) -= R(j, l) R(j, k)
-#pragma unroll
-    for (int q = 0; q < kPcholCols; ++q) {
-      const int k = tid + q * nthr;
-      if (k > j && k < s) {
-        const double rjk = Aw[j * la + k];
-        for (int l = j + 1; l <= k; ++l) Aw[l * la + k] -= Aw[j * la + l] * rjk;
+    // (3) trailing update A(l, k) -= R(j, l) R(j, k), j < l <= k < s; the
+    // loads of four rows are issued before their stores
+    for (int k = j + 1 + lane; k < s; k += kWave) {
+      const double rk = rowj[k];
+      int l = j + 1 + wave;
+      for (; l + 3 * nw <= k; l += 4 * nw) {
+        double* a = Aw + (size_t)l * la + k;
+        const size_t st = (size_t)nw * la;
+        const double a0 = a[0], a1 = a[st], a2 = a[2 * st], a3 = a[3 * st];
+        const double r0 = rowj[l], r1 = rowj[l + nw], r2 = rowj[l + 2 * nw],
+                     r3 = rowj[l + 3 * nw];
+        a[0] = a0 - r0 * rk;
+        a[st] = a1 - r1 * rk;
+        a[2 * st] = a2 - r2 * rk;
+        a[3 * st] = a3 - r3 * rk;
       }
+      for (; l <= k; l += nw) Aw[(size_t)l * la + k] -= rowj[l] * rk;
     }
     __syncthreads();
   }
   if (tid == 0) *p_out = p;
   // Rinv = R^{-1}: thread c owns column c (back substitution R x = e_c)
+  // with the diagonal reciprocals formed first, in parallel
+  for (int c = tid; c < p; c += nthr) rowj[c] = 1.0 / Aw[c * la + c];
+  __syncthreads();
   for (int c = tid; c < p; c += nthr) {
-    Ri[c * la + c] = 1.0 / Aw[c * la + c];
+    Ri[c * la + c] = rowj[c];
     for (int r = c - 1; r >= 0; --r) {
-      double acc = 0.0;
-      for (int t = r + 1; t <= c; ++t) acc += Aw[r * la + t] * Ri[t * la + c];
-      Ri[r * la + c] = -acc / Aw[r * la + r];
+      const double* ar = Aw + r * la;
+      double acc0 = 0.0, acc1 = 0.0;
+      int t = r + 1;
+      for (; t + 1 <= c; t += 2) {
+        acc0 += ar[t] * Ri[t * la + c];
+        acc1 += ar[t + 1] * Ri[(t + 1) * la + c];
+      }
+      if (t <= c) acc0 += ar[t] * Ri[t * la + c];
+      Ri[r * la + c] = -(acc0 + acc1) * rowj[r];
     }
   }
   __syncthreads();
@@ -145,14 +178,15 @@ __global__ __launch_bounds__(kSmallBlock) void k_pchol(
     double omega, double* __restrict__ R, double* __restrict__ Rinv, int ldr,
     int* p_out, double* scratch) {
   __shared__ double buf[kPcholLds];
-  __shared__ double bc[4];
+  __shared__ double rowj[kPcholMaxS];
+  __shared__ double bc[2][2];
   int s = smax;
   if (s_dev) s = min(s, *s_dev);
   // work layout: A (s x s, row-major) | Rinv (s x s, row-major)
   if (2 * (size_t)s * s <= (size_t)kPcholLds)
-    pchol_body(buf, bc, G, ldg, s, omega, R, Rinv, ldr, p_out);
+    pchol_body(buf, rowj, bc, G, ldg, s, omega, R, Rinv, ldr, p_out);
   else
-    pchol_body(scratch, bc, G, ldg, s, omega, R, Rinv, ldr, p_out);
+    pchol_body(scratch, rowj, bc, G, ldg, s, omega, R, Rinv, ldr, p_out);
 }
 
 // Combine both BCGS passes (Alg. 4): R(1:i, k) = W(:, 1:p) + R2(:, 1:p) Z,
@@ -227,7 +261,7 @@ __device__ __forceinline__ void tile_gemm(int m, int n, int k,
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-#pragma unroll 2
+#pragma unroll 4
     for (int kk = 0; kk < k; ++kk) {
       double a[4], b[4];
 #pragma unroll
@@ -255,11 +289,6 @@ __device__ __forceinline__ void tile_gemm(int m, int n, int k,
   }
 }
 
-__device__ __forceinline__ double readlane_f64(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
-}
 
 // Fused tail of one block (one workgroup).
 //  1. Combine the BCGS passes (Alg. 4): R(1:nb, k) = W + R2 Z and
@@ -420,7 +449,25 @@ __device__ __forceinline__ void tail_body(
       double* h = Hn + (size_t)j * nr;
       if (i0 > 0) {
         double carry = h[0];
-        for (int r = 0; r < i0; ++r) {
+        int r = 0;
+        // eight rows per batch: the loads go out before the dependent chain
+        for (; r + 8 <= i0; r += 8) {
+          double b[8], c0[8], s0[8], o[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            b[q] = h[r + 1 + q];
+            c0[q] = css[r + q];
+            s0[q] = sns[r + q];
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            o[q] = c0[q] * carry + s0[q] * b[q];
+            carry = -s0[q] * carry + c0[q] * b[q];
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) h[r + q] = o[q];
+        }
+        for (; r < i0; ++r) {
           const double b = h[r + 1], c0 = css[r], s0 = sns[r];
           h[r] = c0 * carry + s0 * b;
           carry = -s0 * carry + c0 * b;
@@ -523,23 +570,81 @@ __global__ __launch_bounds__(kSmallBlock) void k_block_tail(
 }
 
 // y = Hr(0:k, 0:k)^{-1} g(0:k), column-oriented back substitution.
-__global__ __launch_bounds__(kSmallBlock) void k_back_solve(
+// Every thread first stages the upper triangle into LDS (packed by columns:
+// column j's rows 0..j at j (j + 1) / 2), so the global latency is paid
+// once; wavefront 0 then runs the k sequential steps with the right-hand
+// side in registers (lane l holds rows l, l + 64, ...), broadcasting y_j
+// from its owner lane.  NQ = rows per lane; the triangle is read from
+// global memory when it does not fit in LDS.
+constexpr int kBackLds = 150 * 1024 / 8;
+constexpr int kBackThreads = 1024;
+
+template <int NQ>
+__device__ __forceinline__ void back_solve_wave(const double* T, bool packed,
+                                                const double* __restrict__ Hr,
+                                                int ldh,
+                                                const double* __restrict__ g,
+                                                int k, double* __restrict__ y) {
+  const int lane = threadIdx.x;
+  double b[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int i = lane + kWave * q;
+    b[q] = i < k ? g[i] : 0.0;
+  }
+  auto t = [&](int i, int j) -> double {
+    return packed ? T[(int64_t)j * (j + 1) / 2 + i] : Hr[(int64_t)j * ldh + i];
+  };
+  for (int j = k - 1; j >= 0; --j) {
+    const int owner = j % kWave, qj = j / kWave;
+    double bj = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (q == qj) bj = b[q];
+    const double yj = readlane_f64(bj, owner) / t(j, j);
+    if (lane == 0) y[j] = yj;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int i = lane + kWave * q;
+      if (q <= qj && i < j) b[q] -= t(i, j) * yj;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBackThreads) void k_back_solve(
     const double* __restrict__ Hr, int ldh, const double* __restrict__ g,
     int k, double* __restrict__ y) {
-  __shared__ double b[4096];
-  __shared__ double yj;
-  for (int i = threadIdx.x; i < k; i += kSmallBlock) b[i] = g[i];
-  __syncthreads();
-  for (int j = k - 1; j >= 0; --j) {
-    if (threadIdx.x == 0) {
-      yj = b[j] / Hr[(int64_t)j * ldh + j];
-      y[j] = yj;
+  __shared__ double T[kBackLds];
+  const int64_t npk = (int64_t)k * (k + 1) / 2;
+  const bool packed = npk <= kBackLds;
+  if (packed) {
+    // column-major walk of the full k x k block; rows above the diagonal
+    // are kept
+#pragma unroll 4
+    for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += kBackThreads) {
+      const int j = (int)(e / k), i = (int)(e % k);
+      if (i <= j) T[(int64_t)j * (j + 1) / 2 + i] = Hr[(int64_t)j * ldh + i];
     }
-    __syncthreads();
-    const double v = yj;
-    for (int i = threadIdx.x; i < j; i += kSmallBlock)
-      b[i] -= Hr[(int64_t)j * ldh + i] * v;
-    __syncthreads();
+  }
+  __syncthreads();
+  if (threadIdx.x >= kWave) return;
+  if (k <= 2 * kWave)
+    back_solve_wave<2>(T, packed, Hr, ldh, g, k, y);
+  else if (k <= 4 * kWave)
+    back_solve_wave<4>(T, packed, Hr, ldh, g, k, y);
+  else if (k <= 8 * kWave)
+    back_solve_wave<8>(T, packed, Hr, ldh, g, k, y);
+  else {
+    // long cycles: the right-hand side lives in LDS (the triangle does not
+    // fit there anyway)
+    double* b = T;
+    for (int i = threadIdx.x; i < k; i += kWave) b[i] = g[i];
+    for (int j = k - 1; j >= 0; --j) {
+      const double yj = b[j] / Hr[(int64_t)j * ldh + j];
+      if (threadIdx.x == 0) y[j] = yj;
+      for (int i = threadIdx.x; i < j; i += kWave)
+        b[i] -= Hr[(int64_t)j * ldh + i] * yj;
+    }
   }
 }
 
@@ -553,11 +658,10 @@ __global__ void k_givens_init(double* g, int m, const double* beta) {
 void pchol_ice(const double* G, int ldg, int smax, const int* s_dev,
                double omega, double* R, double* Rinv, int ldr, int* p_out,
                double* scratch, hipStream_t st) {
-  // one wavefront (barriers are nearly free) unless the trailing updates
-  // are large enough to need more lanes
-  const int threads = smax <= 64 ? kWave : kSmallBlock;
-  if (smax > kPcholCols * threads)
-    throw Error{SGM_EINVAL, "partial Cholesky: block larger than 1024"};
+  // thread k owns column k; four wavefronts share the trailing updates
+  const int threads = smax <= 8 ? kWave : kSmallBlock;
+  if (smax > kPcholMaxS || smax > threads)
+    throw Error{SGM_EINVAL, "partial Cholesky: block larger than 256"};
   hipLaunchKernelGGL(k_pchol, dim3(1), dim3(threads), 0, st, G, ldg, smax,
                      s_dev, omega, R, Rinv, ldr, p_out, scratch);
   SGM_CHECK_LAUNCH();
@@ -591,8 +695,8 @@ void back_solve(const double* Hr, int ldh, const double* g, const int* /*kdev*/,
                 int k, double* y, hipStream_t st) {
   if (k <= 0) return;
   if (k > 4096) throw Error{SGM_EINVAL, "restart length above 4096"};
-  hipLaunchKernelGGL(k_back_solve, dim3(1), dim3(kSmallBlock), 0, st, Hr, ldh,
-                     g, k, y);
+  hipLaunchKernelGGL(k_back_solve, dim3(1), dim3(kBackThreads), 0, st, Hr,
+                     ldh, g, k, y);
   SGM_CHECK_LAUNCH();
 }
 

@@ -248,15 +248,13 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_reduce_chunks(
     const int i = (int)(e % ma), j = (int)(e / ma);
     if (sym && (i / 16) > (j / 16)) src = (int64_t)i * ma + j;
     int64_t c = w;
-    for (; c + 3 * kRedWaves < nchunks; c += 4 * kRedWaves) {
-      const double a0 = part[c * stride + src];
-      const double a1 = part[(c + kRedWaves) * stride + src];
-      const double a2 = part[(c + 2 * kRedWaves) * stride + src];
-      const double a3 = part[(c + 3 * kRedWaves) * stride + src];
-      s += a0;
-      s += a1;
-      s += a2;
-      s += a3;
+    // eight loads in flight per lane; the sum keeps the chunk order
+    for (; c + 7 * kRedWaves < nchunks; c += 8 * kRedWaves) {
+      double a[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = part[(c + q * kRedWaves) * stride + src];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += a[q];
     }
     for (; c < nchunks; c += kRedWaves) s += part[c * stride + src];
   }
