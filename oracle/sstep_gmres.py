@@ -408,8 +408,8 @@ def block_orth(Q, i, V, omega, work_dtype=np.float64, cond="ice"):
 def hessenberg_block(Hraw, i, p, R_top, R_kk, B):
     """New Hessenberg columns i..i+p-1 (1-based) of the block started at Q_i.
 
-    The paper only says "assemble the upper Hessenberg matrix" (Alg. 1/4) and
-    refers to the s-step literature.  Derivation used here: with
+    Alg. 1/4 name this step without giving a formula and point to the
+    s-step literature.  Derivation used here: with
     V_{1:p+1} = Q_{1:i+p} Rt, Rt = [e_i | R(1:i+p, k)], and A V_{1:p} =
     V_{1:p+1} B_p, split Rt(1:i+p-1, 1:p) = [X; T] (X: rows 1..i-1, T: rows
     i..i+p-1, upper triangular with T_11 = 1).  The Arnoldi relation
@@ -555,16 +555,23 @@ class _Engine:
         return V[:, 1:]
 
     def finish_prephase(self, Hraw, m0, st: _State):
-        """Ritz values of H(1:m0, 1:m0) from the column-wise pre-phase
-        (Sec. 3.4: "obtained from s iterations of classical Arnoldi or GMRES"),
-        Leja order, (scaled) Newton records, and the initial step size from
-        the estimator of Sec. 3.5 (scaled Newton only)."""
-        o = self.o
+        """Ritz values of H(1:m0, 1:m0) from the column-wise pre-phase (Sec.
+        3.4 takes them from a short run of standard Arnoldi / GMRES), Leja
+        order, (scaled) Newton records, and the initial step size from the
+        estimator of Sec. 3.5 (scaled Newton only)."""
         ritz = (np.linalg.eigvals(Hraw[:m0, :m0]) if m0 > 0
                 else np.array([0.0 + 0.0j]))
+        self.set_shifts(st, ritz, estimate=m0 > 0)
+
+    def set_shifts(self, st: _State, ritz, estimate=True):
+        """Shifts from Ritz values (Leja order, recurrence records) and the
+        initial step size of Sec. 3.5.  Reading: shifts the caller passes
+        in stand in for the pre-phase's Ritz values, so the estimator sets
+        the initial step size from them in the same way."""
+        o = self.o
         st.shifts = _make_shifts(o.basis, ritz)
         st.s_init = o.s_max
-        if o.basis == "scaled_newton" and o.use_estimator and m0 > 0:
+        if o.basis == "scaled_newton" and o.use_estimator and estimate:
             s0, _ = estimator(st.shifts.ritz, st.shifts.gamma, self.u,
                               self.omega_est)
             st.s0_est = s0
@@ -697,7 +704,7 @@ def solve(A, b, x0=None, opts: Options | None = None) -> Result:
     Q = np.zeros((n, m + 1), dtype=eng.wd, order="F")
     st = _State(None, o.s_max)
     if o.shifts is not None:
-        st.shifts = _make_shifts(o.basis, np.asarray(o.shifts, dtype=complex))
+        eng.set_shifts(st, np.asarray(o.shifts, dtype=complex))
     elif o.basis == "monomial":
         st.shifts = monomial_shifts()
     beta = beta0
@@ -772,7 +779,7 @@ def solve_ir(A, b, x0=None, opts: Options | None = None, inner_tol=1e-4,
     Q = np.zeros((n, inner.restart + 1), dtype=np.float32, order="F")
     st = _State(None, inner.s_max)
     if o.shifts is not None:
-        st.shifts = _make_shifts(o.basis, np.asarray(o.shifts, dtype=complex))
+        eng.set_shifts(st, np.asarray(o.shifts, dtype=complex))
     elif o.basis == "monomial":
         st.shifts = monomial_shifts()
     iters = 0
