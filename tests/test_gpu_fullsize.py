@@ -1,0 +1,199 @@
+"""GPU checks at the full sizes of the five synthetic workloads, in the
+launch configuration the benchmark uses (matrix analysed once, workspace
+from the library's size query, default stream).
+
+The oracle cannot run whole solves at these sizes, so every test checks
+what can be computed independently of the HIP path:
+- float64 true residuals of the returned solution (scipy CSR product on the
+  host);
+- the first GMRES residuals: the first iterations are the column-wise
+  CGS2 steps of the Ritz pre-phase, which GMRES fixes uniquely, so they
+  must match classical MGS-GMRES (the oracle's baseline) run for a few
+  steps on the host;
+- the oracle's whole first restart cycle where it finishes in seconds;
+- invariants of the method: residual estimates non-increasing inside a
+  cycle, block sizes non-increasing inside a cycle and bounded by the
+  initial step size, the Givens estimate at a cycle end equal to the true
+  residual;
+- sampled SpMV rows and gradient entries, computed one by one.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import sstep_gmres as o
+
+pytestmark = pytest.mark.gpu
+
+
+def csr(A):
+    return o.csr_matrix(A.n, A.row_ptr, A.col, A.val)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def split_cycles(s_hist, restart):
+    """Block sizes grouped per restart cycle (a cycle ends when its blocks
+    have produced `restart` columns, or at a breakdown)."""
+    cycles, cur, tot = [], [], 0
+    for p in s_hist:
+        cur.append(p)
+        tot += max(p, 1)
+        if tot >= restart or p == 0:
+            cycles.append(cur)
+            cur, tot = [], 0
+    if cur:
+        cycles.append(cur)
+    return cycles
+
+
+def check_cycle_invariants(gpu, restart, m0, s_max):
+    s_init = gpu.info["s_init"]
+    assert 1 <= s_init <= s_max
+    cycles = split_cycles(list(gpu.s_hist), restart)
+    h = np.asarray(gpu.res_hist)
+    pos = 0
+    for c, blocks in enumerate(cycles):
+        body = blocks[m0:] if c == 0 else blocks
+        if c == 0:
+            assert blocks[:m0] == [1] * min(m0, len(blocks))   # pre-phase
+        assert all(1 <= p <= s_init for p in body if p > 0)
+        assert all(a >= b for a, b in zip(body, body[1:]))     # s never grows
+        ncol = min(sum(max(p, 1) for p in blocks), h.size - pos)
+        seg = h[pos:pos + ncol]
+        assert np.all(seg[1:] <= seg[:-1] * (1 + 1e-12))       # GMRES
+        pos += ncol
+    assert pos == h.size
+
+
+def spmv_rows_match(A, y, x, rows):
+    for r in rows:
+        a, b = A.row_ptr[r], A.row_ptr[r + 1]
+        prod = A.val[a:b] * x[A.col[a:b]]
+        ref = prod.sum()
+        bound = 8 * 2.0 ** -52 * np.abs(prod).sum() + 1e-300
+        assert abs(y[r] - ref) <= bound, (r, y[r], ref)
+
+
+def test_poisson128_bench_workload(lib):
+    """3D Poisson 128^3, the benchmark configuration: float64 and float32-IR
+    solves to 1e-10 (true residual on the host), the oracle's first restart
+    cycle block by block, sampled SpMV rows."""
+    A = W.poisson_3d(128)
+    M = csr(A)
+    b = W.rhs(A.n, 2)
+    G = lib.Matrix.from_csr(A)
+    kw = dict(s_max=32, restart=128, tol=1e-10)
+    gpu = lib.solve(G, b, max_restarts=1000, **kw)
+    x = gpu.x.cpu().numpy()
+    assert gpu.status == lib.OK
+    true = np.linalg.norm(b - M @ x) / np.linalg.norm(b)
+    assert true <= 1e-10
+    assert abs(gpu.info["rel_res_true"] - true) <= 1e-6 * true
+    check_cycle_invariants(gpu, 128, 32, 32)
+    # the oracle's first cycle (32 pre-phase steps + blocks of 32)
+    ref = o.solve(M, b, opts=o.Options(max_restarts=0, **kw))
+    assert gpu.info["s0_est"] == ref.s0_est
+    assert list(gpu.s_hist[:len(ref.s_hist)]) == ref.s_hist
+    h = np.asarray(gpu.res_hist[:len(ref.res_hist)])
+    hr = np.asarray(ref.res_hist)
+    assert np.all(np.abs(h - hr) <= 1e-6 * hr)
+    # float32 inner cycles, float64 refinement: same final tolerance
+    g32 = lib.solve(G, b, precision="fp32_ir", inner_tol=1e-6, max_outer=500,
+                    max_restarts=1000, **kw)
+    x32 = g32.x.cpu().numpy()
+    assert g32.status == lib.OK
+    assert np.linalg.norm(b - M @ x32) / np.linalg.norm(b) <= 1e-10
+    assert rel(x32, x) <= 1e-6     # kappa(A) ~ 7e3 times 2e-10
+    # SpMV: sampled rows against the CSR sum
+    rng = np.random.default_rng(20)
+    xr = rng.standard_normal(A.n)
+    y = G.spmv(xr).cpu().numpy()
+    spmv_rows_match(A, y, xr, rng.choice(A.n, 2048, replace=False))
+
+
+def test_varcd192_jacobi_first_cycle(lib):
+    """3D variable-coefficient convection-diffusion 192^3 with right Jacobi,
+    s_max 128, restart 256: one float64 cycle.  The first 8 residuals equal
+    MGS-GMRES on the column-scaled matrix; the cycle-end estimate equals the
+    true residual; block sizes and residuals obey the cycle invariants."""
+    A = W.var_conv_diff_3d(192, 3)
+    M = csr(A)
+    b = W.rhs(A.n, 3)
+    G = lib.Matrix.from_csr(A)
+    gpu = lib.solve(G, b, s_max=128, restart=256, tol=1e-10,
+                    precond="jacobi", max_restarts=0)
+    assert gpu.status in (lib.OK, lib.NOT_CONVERGED)
+    check_cycle_invariants(gpu, 256, 128, 128)
+    x = gpu.x.cpu().numpy()
+    true = np.linalg.norm(b - M @ x) / np.linalg.norm(b)
+    est = gpu.res_hist[-1]
+    assert abs(true - est) <= 1e-6 * true
+    assert abs(gpu.info["rel_res_true"] - true) <= 1e-6 * true
+    As, _ = o.jacobi_column_scaled(M)
+    _, h8, _ = o.mgs_gmres(As, b, restart=8, tol=1e-300, max_restarts=0)
+    assert np.all(np.abs(np.asarray(gpu.res_hist[:8]) - h8) <= 1e-8 * np.asarray(h8))
+
+
+def test_banded_1m_adjoint(lib):
+    """Random banded nonsymmetric matrix, n = 1M, 27 nonzeros per row:
+    forward and adjoint float64 solves through the differentiable solve.
+    Checks: both true residuals on the host, the duality identity
+    lambda^T b = g^T x, and sampled gradient entries of the CSR values."""
+    import torch
+    A, b, xs = W.banded_problem(1_000_000, seed=4, band=1000)
+    M = csr(A)
+    G = lib.Matrix.from_csr(A)
+    opts = dict(s_max=32, restart=128, tol=1e-12, max_restarts=200)
+    vals = torch.tensor(A.val, device="cuda", requires_grad=True)
+    bt = torch.tensor(b, device="cuda", requires_grad=True)
+    x = lib.sstep_solve(vals, bt, G, **opts)
+    loss = 0.5 * ((x - torch.tensor(xs, device="cuda")) ** 2).sum()
+    loss.backward()
+    xh = x.detach().cpu().numpy()
+    lam = bt.grad.cpu().numpy()
+    gv = vals.grad.cpu().numpy()
+    g = xh - xs
+    assert np.linalg.norm(b - M @ xh) <= 1e-12 * np.linalg.norm(b)
+    assert np.linalg.norm(g - M.T @ lam) <= 1e-12 * np.linalg.norm(g)
+    assert abs(lam @ b - g @ xh) <= 1e-10 * np.linalg.norm(lam) * np.linalg.norm(b)
+    rng = np.random.default_rng(21)
+    ks = rng.choice(A.nnz, 4096, replace=False)
+    rows = np.searchsorted(A.row_ptr, ks, side="right") - 1
+    assert np.array_equal(gv[ks], -lam[rows] * xh[A.col[ks]])
+
+
+def test_aniso4096_fp32_ir_one_outer_step(lib):
+    """2D anisotropic diffusion 4096^2 (n = 16.8M): one float32 inner cycle
+    (200 pre-phase steps, blocks up to s = 200, restart 400) inside float64
+    refinement, then the backward solve for the gradient w.r.t. b.  The
+    first 8 inner residuals match float64 MGS-GMRES to float32 accuracy;
+    the float64 true residual after the step matches the inner estimate; the
+    cycle invariants hold; the backward solve reduces its residual."""
+    import torch
+    A = W.aniso_diffusion_2d(4096)
+    M = csr(A)
+    b = W.rhs(A.n, 5)
+    G = lib.Matrix.from_csr(A)
+    kw = dict(s_max=200, restart=400, tol=1e-10, precision="fp32_ir",
+              inner_tol=1e-6, max_outer=1)
+    gpu = lib.solve(G, b, **kw)
+    assert gpu.status == lib.NOT_CONVERGED and gpu.info["outer_iters"] == 1
+    check_cycle_invariants(gpu, 400, 200, 200)
+    x = gpu.x.cpu().numpy()
+    true = np.linalg.norm(b - M @ x) / np.linalg.norm(b)
+    est = gpu.res_hist[-1]
+    assert true < 1.0 and abs(true - est) <= 1e-3 * est + 1e-5
+    _, h8, _ = o.mgs_gmres(M, b, restart=8, tol=1e-300, max_restarts=0)
+    assert np.all(np.abs(np.asarray(gpu.res_hist[:8]) - h8) <= 1e-4 * np.asarray(h8))
+    # backward w.r.t. b: the transposed solve with the same options
+    bt = torch.tensor(b, device="cuda", requires_grad=True)
+    vals = torch.tensor(A.val, device="cuda")
+    xg = lib.sstep_solve(vals, bt, G, **kw)
+    (0.5 * (xg ** 2).sum()).backward()
+    lam = bt.grad.cpu().numpy()
+    xgh = xg.detach().cpu().numpy()
+    assert np.all(np.isfinite(lam))
+    assert np.linalg.norm(xgh - M.T @ lam) <= 0.5 * np.linalg.norm(xgh)
