@@ -111,6 +111,10 @@ struct Sell {
   int64_t* ptr = nullptr;   // [nslices + 1]
   int32_t* width = nullptr; // [nslices]
   int32_t* col = nullptr;   // [nnz_padded]
+  // [nnz_padded] col - row as 16 bits, present when every entry's distance
+  // from the diagonal fits (then the SpMV reads these 2-byte deltas
+  // instead of the 4-byte columns); rows past n point at row n - 1
+  int16_t* dcol = nullptr;
   int64_t* src = nullptr;   // [nnz_padded] CSR index of each entry, -1 = pad
   double* val64 = nullptr;  // [nnz_padded]
   float* val32 = nullptr;   // [nnz_padded]

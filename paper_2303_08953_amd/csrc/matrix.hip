@@ -88,6 +88,43 @@ __global__ void k_sell_fill(const int32_t* rp, const int32_t* col,
   }
 }
 
+// Largest |col - row| over the real rows of a SELL matrix (integer max:
+// the result does not depend on the order of the atomics).
+__global__ void k_sell_max_delta(const int32_t* scol, const int64_t* ptr,
+                                 const int32_t* width, int64_t n,
+                                 int64_t nslices, int32_t* out) {
+  int64_t s = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave;
+  int lane = threadIdx.x % kWave;
+  if (s >= nslices) return;
+  int64_t r = s * kSlice + lane;
+  int64_t base = ptr[s] + lane;
+  int w = width[s];
+  int32_t m = 0;
+  if (r < n)
+    for (int k = 0; k < w; ++k) {
+      const int64_t d = (int64_t)scol[base + (int64_t)k * kSlice] - r;
+      const int64_t a = d < 0 ? -d : d;
+      m = max(m, (int32_t)min(a, (int64_t)INT32_MAX));
+    }
+  for (int off = kWave / 2; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+  if (lane == 0) atomicMax(out, m);
+}
+
+__global__ void k_sell_deltas(const int32_t* scol, const int64_t* ptr,
+                              const int32_t* width, int64_t n, int64_t nslices,
+                              int16_t* dcol) {
+  int64_t s = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave;
+  int lane = threadIdx.x % kWave;
+  if (s >= nslices) return;
+  int64_t r = s * kSlice + lane;
+  int64_t base = ptr[s] + lane;
+  int w = width[s];
+  for (int k = 0; k < w; ++k) {
+    const int64_t e = base + (int64_t)k * kSlice;
+    dcol[e] = (int16_t)(r < n ? (int64_t)scol[e] - r : (n - 1) - r);
+  }
+}
+
 __global__ void k_sell_values(const int64_t* src, int64_t m,
                               const double* val, double* v64, float* v32) {
   int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -173,6 +210,26 @@ void sell_build(Sell& S, int64_t n, const int32_t* rp, const int32_t* col,
                      dim3(wpb * kWave), 0, st, rp, col, perm, n, S.nslices,
                      S.ptr, S.width, S.col, S.src);
   SGM_CHECK_LAUNCH();
+  // 16-bit column deltas when every entry lies within 32767 of the
+  // diagonal (stencils, banded matrices)
+  int32_t* dmax = dmalloc<int32_t>(1);
+  SGM_HIP(hipMemsetAsync(dmax, 0, sizeof(int32_t), st));
+  hipLaunchKernelGGL(k_sell_max_delta, dim3(grid1(S.nslices, wpb)),
+                     dim3(wpb * kWave), 0, st, S.col, S.ptr, S.width, n,
+                     S.nslices, dmax);
+  SGM_CHECK_LAUNCH();
+  int32_t hmax = 0;
+  SGM_HIP(hipMemcpyAsync(&hmax, dmax, sizeof(int32_t), hipMemcpyDeviceToHost,
+                         st));
+  SGM_HIP(hipStreamSynchronize(st));
+  dfree(dmax);
+  if (hmax <= 32767 && n >= 1) {
+    S.dcol = dmalloc<int16_t>(total);
+    hipLaunchKernelGGL(k_sell_deltas, dim3(grid1(S.nslices, wpb)),
+                       dim3(wpb * kWave), 0, st, S.col, S.ptr, S.width, n,
+                       S.nslices, S.dcol);
+    SGM_CHECK_LAUNCH();
+  }
 }
 
 void sell_fill_values(const Sell& S, const double* val, hipStream_t st) {
@@ -185,6 +242,7 @@ void sell_free(Sell& S) {
   dfree(S.ptr);
   dfree(S.width);
   dfree(S.col);
+  dfree(S.dcol);
   dfree(S.src);
   dfree(S.val64);
   dfree(S.val32);

@@ -13,16 +13,19 @@ constexpr int kSlicesPerBlock = kSpmvBlock / kWave;
 // x, xprev and y are columns of a block of vectors with layout XV (row r of
 // a column at column base + XV.row_off(r)); the plain and residual
 // epilogues use contiguous vectors (column-major view).
-template <typename T, int EPI>
+// IDX is int32_t (absolute columns) or int16_t (column - row).
+template <typename T, int EPI, typename IDX>
 __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
     const int64_t* __restrict__ ptr, const int32_t* __restrict__ width,
-    const int32_t* __restrict__ col, const T* __restrict__ val, QView<T> XV,
+    const IDX* __restrict__ col, const T* __restrict__ val, QView<T> XV,
     const T* __restrict__ x, const T* __restrict__ xprev, T* __restrict__ y,
     const double* __restrict__ b, double* __restrict__ part, int64_t n,
     int64_t nslices, const double* __restrict__ rec, int j) {
   const int64_t s = (int64_t)blockIdx.x * kSlicesPerBlock + threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   const int64_t r = s * kSlice + lane;
+  // column of an entry: absolute, or the row plus a 16-bit delta
+  const int32_t cb = sizeof(IDX) == 2 ? (int32_t)r : 0;
   T sum = 0;
   if (s < nslices) {
     const int64_t base = ptr[s] + lane;
@@ -30,8 +33,8 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
     int k = 0;
     for (; k + 4 <= w; k += 4) {
       const int64_t e = base + (int64_t)k * kSlice;
-      const int32_t c0 = col[e], c1 = col[e + kSlice], c2 = col[e + 2 * kSlice],
-                    c3 = col[e + 3 * kSlice];
+      const int32_t c0 = cb + col[e], c1 = cb + col[e + kSlice],
+                    c2 = cb + col[e + 2 * kSlice], c3 = cb + col[e + 3 * kSlice];
       const T v0 = val[e], v1 = val[e + kSlice], v2 = val[e + 2 * kSlice],
               v3 = val[e + 3 * kSlice];
       sum += v0 * x[XV.row_off(c0)];
@@ -41,7 +44,7 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
     }
     for (; k < w; ++k) {
       const int64_t e = base + (int64_t)k * kSlice;
-      sum += val[e] * x[XV.row_off(col[e])];
+      sum += val[e] * x[XV.row_off(cb + col[e])];
     }
   }
   if constexpr (EPI == EPI_PLAIN) {
@@ -155,23 +158,29 @@ inline unsigned g1(int64_t n) {
 template <typename T>
 void spmv_plain(const Sell& S, const T* val, const T* x, T* y,
                 hipStream_t st) {
-  hipLaunchKernelGGL((k_spmv<T, EPI_PLAIN>), dim3(spmv_grid(S)),
-                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, S.col, val,
-                     colmajor_view<T>(nullptr, 0), x, (const T*)nullptr, y,
-                     (const double*)nullptr, (double*)nullptr, S.n, S.nslices,
-                     (const double*)nullptr, 0);
+#define SGM_SPMV(IDX, colp)                                                    \
+  hipLaunchKernelGGL((k_spmv<T, EPI_PLAIN, IDX>), dim3(spmv_grid(S)),          \
+                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, val,       \
+                     colmajor_view<T>(nullptr, 0), x, (const T*)nullptr, y,    \
+                     (const double*)nullptr, (double*)nullptr, S.n, S.nslices, \
+                     (const double*)nullptr, 0)
+  if (S.dcol) SGM_SPMV(int16_t, S.dcol); else SGM_SPMV(int32_t, S.col);
+#undef SGM_SPMV
   SGM_CHECK_LAUNCH();
 }
 
 template <typename T>
 void spmv_mpk(const Sell& S, const T* val, QView<T> Q, int jx, int jprev,
               int jy, const double* rec, int j, hipStream_t st) {
-  hipLaunchKernelGGL((k_spmv<T, EPI_MPK>), dim3(spmv_grid(S)),
-                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, S.col, val, Q,
-                     (const T*)Q.col(jx),
-                     jprev >= 0 ? (const T*)Q.col(jprev) : (const T*)nullptr,
-                     Q.col(jy), (const double*)nullptr, (double*)nullptr, S.n,
-                     S.nslices, rec, j);
+  const T* xp = jprev >= 0 ? (const T*)Q.col(jprev) : (const T*)nullptr;
+#define SGM_SPMV(IDX, colp)                                                   \
+  hipLaunchKernelGGL((k_spmv<T, EPI_MPK, IDX>), dim3(spmv_grid(S)),           \
+                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, val, Q,   \
+                     (const T*)Q.col(jx), xp, Q.col(jy),                      \
+                     (const double*)nullptr, (double*)nullptr, S.n,           \
+                     S.nslices, rec, j)
+  if (S.dcol) SGM_SPMV(int16_t, S.dcol); else SGM_SPMV(int32_t, S.col);
+#undef SGM_SPMV
   SGM_CHECK_LAUNCH();
 }
 
@@ -179,11 +188,14 @@ int64_t resid_partials(const Sell& S) { return spmv_grid(S); }
 
 int64_t spmv_resid(const Sell& S, const double* val, const double* x,
                    const double* b, double* r, double* part, hipStream_t st) {
-  hipLaunchKernelGGL((k_spmv<double, EPI_RESID>), dim3(spmv_grid(S)),
-                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, S.col, val,
-                     colmajor_view<double>(nullptr, 0), x,
-                     (const double*)nullptr, r, b, part, S.n, S.nslices,
-                     (const double*)nullptr, 0);
+#define SGM_SPMV(IDX, colp)                                                   \
+  hipLaunchKernelGGL((k_spmv<double, EPI_RESID, IDX>), dim3(spmv_grid(S)),    \
+                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, val,      \
+                     colmajor_view<double>(nullptr, 0), x,                    \
+                     (const double*)nullptr, r, b, part, S.n, S.nslices,      \
+                     (const double*)nullptr, 0)
+  if (S.dcol) SGM_SPMV(int16_t, S.dcol); else SGM_SPMV(int32_t, S.col);
+#undef SGM_SPMV
   SGM_CHECK_LAUNCH();
   return spmv_grid(S);
 }

@@ -106,31 +106,45 @@ constexpr int kBlock = 256;  // 4 wavefronts per workgroup
 
 // ------------------------------------------------------------- A^T B
 // C = Q(:, a0:a0+ma)^T Q(:, b0:b0+nb) over 16-row batches of Q.
-// Grid: 1-D, chunks * ntiles workgroups (chunks a multiple of 8).  XCD-aware
-// decode: workgroup id -> (xcd = id % 8, slot = id / 8); the ntiles output
-// tiles of one row chunk get consecutive slots on the same XCD, so they run
-// together and share that XCD's L2 for the rows they all read.
-// Each wavefront consumes 16-row batches; lane (g = l/16, c = l%16) loads
-// rows 4g..4g+3 of one column as a 4-vector, and MFMA step t pairs row
-// 4g + t of A with the same row of B.  A 16-row batch never straddles a
-// row panel, so one row offset per batch serves every column.
-template <typename T, int MT, int NT>
+// The output is cut into wave tiles of MT x NT 16x16 MFMA tiles.  A
+// workgroup covers WT consecutive wave tiles over one row chunk: wavefront
+// w takes wave tile w % WT and every (4/WT)-th batch of the chunk starting
+// at batch w / WT (its row phase); with WT < 4 the row phases are summed
+// through LDS in a fixed order.  Spreading the tiles over the wavefronts
+// keeps the registers per wavefront low (4 float64 or 8 float32 tiles), so
+// several workgroups share a CU and many batches are in flight; the A
+// columns of different tiles are read once, the B columns they share come
+// from L2.
+// Grid: 1-D, chunks * ngroups workgroups (chunks a multiple of 8).
+// XCD-aware decode: workgroup id -> (xcd = id % 8, slot = id / 8); the
+// ngroups tile groups of one row chunk get consecutive slots on the same
+// XCD and share its L2.
+// Lane (g = l/16, c = l%16) loads rows 4g..4g+3 of one column as a
+// 4-vector, and MFMA step t pairs row 4g + t of A with the same row of B.
+// A 16-row batch never straddles a row panel, so one row offset per batch
+// serves every column.
+template <typename T, int MT, int NT, int WT>
 __global__ __launch_bounds__(kBlock) void k_gemm_tn(
     QView<const T> Q, int a0, int ma, int b0c, int nb,
-    const int* __restrict__ ncount, int64_t nbatches, int tiles_n, int ntiles,
-    int chunks, double* __restrict__ part) {
+    const int* __restrict__ ncount, int64_t nbatches, int wtiles_n,
+    int n_wtiles, int ngroups, int chunks, double* __restrict__ part) {
   typedef typename Vec4<T>::type V;
+  constexpr int RP = (kBlock / kWave) / WT;  // row phases
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int g = lane / 16, c16 = lane % 16;
+  const int wt = wave % WT, rp = wave / WT;
   const int id = blockIdx.x;
   const int xcd = id % 8, slot = id / 8;
-  const int tile = slot % ntiles;
-  const int chunk = (slot / ntiles) * 8 + xcd;
-  const int tm = tile / tiles_n, tn = tile % tiles_n;
+  const int group = slot % ngroups;
+  const int chunk = (slot / ngroups) * 8 + xcd;
+  const int t = group * WT + wt;
+  const int tm = t / wtiles_n, tn = t % wtiles_n;
   const int m0 = tm * 16 * MT, n0 = tn * 16 * NT;
   const int nbe = ncount ? min(nb, *ncount) : nb;
   const int64_t b0 = nbatches * chunk / chunks;
   const int64_t b1 = nbatches * (chunk + 1) / chunks;
+  // M tiles of this wave tile with a valid column (0 for a spare wavefront)
+  const int mt_live = t < n_wtiles ? min(MT, (ma - m0 + 15) / 16) : 0;
 
   // per-lane column offsets; a column past the end reads column a0 / b0c
   int64_t oa[MT], ob[NT];
@@ -149,18 +163,13 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(
   for (int i = 0; i < MT; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[i][j] = vzero<V>();
-  // M tiles with no valid column contribute nothing: skip their MFMAs
-  const int mt_live = min(MT, (ma - m0 + 15) / 16);
 
   // Register double buffering: the loads of the next batch are in flight
-  // while the MFMAs of the current one run.
-  constexpr int kStep = kBlock / kWave;
+  // while the MFMAs of the current one run.  Loads are unconditional: a
+  // column past the end reads a valid column instead; it only feeds output
+  // rows that are never stored or output columns that are zeroed at the
+  // store.
   V af[MT], bf[NT], an[MT], bn[NT];
-  // Loads are unconditional and unmasked: a column past the end reads
-  // column 0 instead; it only feeds output rows that are never stored or
-  // output columns that are zeroed at the store.  With no branch or select
-  // between a load and its MFMA, the compiler waits for the current batch
-  // only while the next one is in flight.
   auto load = [&](int64_t bt, V (&a)[MT], V (&b)[NT]) {
     const T* rb = Q.base + Q.row_off(bt * 16);
 #pragma unroll
@@ -168,47 +177,52 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(
 #pragma unroll
     for (int j = 0; j < NT; ++j) b[j] = *reinterpret_cast<const V*>(rb + ob[j]);
   };
-  int64_t bt = b0 + wave;
-  if (bt < b1) load(bt, af, bf);
-  for (; bt < b1; bt += kStep) {
-    const bool more = bt + kStep < b1;
-    if (more) load(bt + kStep, an, bn);
+  if (mt_live > 0) {
+    int64_t bt = b0 + rp;
+    if (bt < b1) load(bt, af, bf);
+    for (; bt < b1; bt += RP) {
+      const bool more = bt + RP < b1;
+      if (more) load(bt + RP, an, bn);
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int i = 0; i < MT; ++i) {
-        if (i >= mt_live) continue;
+        for (int i = 0; i < MT; ++i) {
+          if (i >= mt_live) continue;
 #pragma unroll
-        for (int j = 0; j < NT; ++j) acc[i][j] = mfma(af[i][t], bf[j][t], acc[i][j]);
+          for (int j = 0; j < NT; ++j) acc[i][j] = mfma(af[i][q], bf[j][q], acc[i][j]);
+        }
+      if (more) {
+#pragma unroll
+        for (int i = 0; i < MT; ++i) af[i] = an[i];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) bf[j] = bn[j];
       }
-    if (more) {
-#pragma unroll
-      for (int i = 0; i < MT; ++i) af[i] = an[i];
-#pragma unroll
-      for (int j = 0; j < NT; ++j) bf[j] = bn[j];
     }
   }
 
-  // Fixed-order reduction of the 4 wavefronts through LDS.
+  // Fixed-order sum of the row phases of each wave tile through LDS: row
+  // phase RP-1 first, row phase 0 adds the sum and stores.
   constexpr int NE = MT * NT * 4;
-  __shared__ double red[NE * kWave];
-  for (int w = kBlock / kWave - 1; w >= 1; --w) {
-    if (wave == w) {
+  __shared__ double red[RP > 1 ? WT * NE * kWave : 1];
+  if constexpr (RP > 1) {
+    for (int r = RP - 1; r >= 1; --r) {
+      if (rp == r) {
 #pragma unroll
-      for (int i = 0; i < MT; ++i)
+        for (int i = 0; i < MT; ++i)
 #pragma unroll
-        for (int j = 0; j < NT; ++j)
+          for (int j = 0; j < NT; ++j)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int e = ((i * NT + j) * 4 + q) * kWave + lane;
-            double v = (double)acc[i][j][q];
-            if (w < kBlock / kWave - 1) v += red[e];
-            red[e] = v;
-          }
+            for (int q = 0; q < 4; ++q) {
+              const int e = (wt * NE + (i * NT + j) * 4 + q) * kWave + lane;
+              double v = (double)acc[i][j][q];
+              if (r < RP - 1) v += red[e];
+              red[e] = v;
+            }
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  if (wave == 0) {
+  if (rp == 0 && t < n_wtiles) {
     double* out = part + (int64_t)chunk * ma * nb;
 #pragma unroll
     for (int i = 0; i < MT; ++i)
@@ -216,12 +230,14 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(
       for (int j = 0; j < NT; ++j)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int e = ((i * NT + j) * 4 + q) * kWave + lane;
           const int row = m0 + i * 16 + drow<T>(g, q);
           const int col = n0 + j * 16 + c16;
-          if (row < ma && col < nb)
-            out[(int64_t)col * ma + row] =
-                col < nbe ? (double)acc[i][j][q] + red[e] : 0.0;
+          if (row < ma && col < nb) {
+            double v = (double)acc[i][j][q];
+            if constexpr (RP > 1)
+              v += red[(wt * NE + (i * NT + j) * 4 + q) * kWave + lane];
+            out[(int64_t)col * ma + row] = col < nbe ? v : 0.0;
+          }
         }
   }
 }
@@ -532,9 +548,9 @@ __global__ __launch_bounds__(256) void k_gemv_update(
 // enough partials that their reduction stays cheap.
 constexpr int kTargetGroups = 512;
 
-int pick_chunks(int ntiles, int64_t nbatches, int64_t per_chunk,
-                const Partials& P) {
-  int64_t target = (kTargetGroups + ntiles - 1) / ntiles;
+int pick_chunks(int target_groups, int ntiles, int64_t nbatches,
+                int64_t per_chunk, const Partials& P) {
+  int64_t target = (target_groups + ntiles - 1) / ntiles;
   int64_t maxc = nbatches / 4;  // at least one batch per wavefront
   if (target > maxc) target = maxc;
   int64_t capc = per_chunk > 0 ? P.cap / per_chunk : target;
@@ -546,42 +562,59 @@ int pick_chunks(int ntiles, int64_t nbatches, int64_t per_chunk,
   return (int)target;
 }
 
-template <typename T, int MT, int NT>
+template <typename T, int MT, int NT, int WT>
 void launch_gemm_tn(QView<const T> Q, int a0, int ma, int b0, int nb,
-                    const int* ncount, int64_t nbatches, int tiles_n,
-                    int ntiles, int chunks, double* part, hipStream_t st) {
-  hipLaunchKernelGGL((k_gemm_tn<T, MT, NT>), dim3(chunks * ntiles),
+                    const int* ncount, int64_t nbatches, int wtiles_n,
+                    int n_wtiles, int ngroups, int chunks, double* part,
+                    hipStream_t st) {
+  hipLaunchKernelGGL((k_gemm_tn<T, MT, NT, WT>), dim3(chunks * ngroups),
                      dim3(kBlock), 0, st, Q, a0, ma, b0, nb, ncount, nbatches,
-                     tiles_n, ntiles, chunks, part);
+                     wtiles_n, n_wtiles, ngroups, chunks, part);
   SGM_CHECK_LAUNCH();
 }
 
 }  // namespace
 
+// Shape choice (from a sweep over the block shapes of the solver on
+// 2M-row panels): NT column tiles per wave tile (1, 2 or 4); MT row tiles
+// up to MT * NT = 8 (float64) or 16 (float32); WT = 2 wave tiles per
+// workgroup when there are at least two, else one wave tile with the
+// wavefronts on four row phases (splitting the output further makes the
+// wavefronts re-read the shared B columns and costs more than it gains).
+// The grid holds about 256 workgroups for the largest wave tiles and up to
+// 1024 for the smallest, so the bytes in flight stay near the same level.
 template <typename T>
 void gemm_tn(QView<const T> Q, int a0, int ma, int b0, int nb,
              const int* ncount, int64_t nrows, double* C, int ldc,
              Partials& P, hipStream_t st) {
   if (ma <= 0 || nb <= 0) return;
   const int mt_all = (ma + 15) / 16, nt_all = (nb + 15) / 16;
-  int NT = nt_all <= 1 ? 1 : (nt_all <= 2 ? 2 : 4);
-  const int mt_cap = sizeof(T) == 8 ? (NT == 4 ? 2 : 8) : 4;
+  const int NT = nt_all <= 1 ? 1 : (nt_all <= 2 ? 2 : 4);
+  const int max_tiles = sizeof(T) == 8 ? 8 : 16;
   int MT = 1;
-  while (MT < mt_all && MT < mt_cap) MT *= 2;
-  const int tiles_n = (nt_all + NT - 1) / NT;
-  const int tiles_m = (mt_all + MT - 1) / MT;
-  const int ntiles = tiles_m * tiles_n;
+  while (MT < mt_all && MT < 8 && 2 * MT * NT <= max_tiles) MT *= 2;
+  const int wtiles_n = (nt_all + NT - 1) / NT;
+  const int wtiles_m = (mt_all + MT - 1) / MT;
+  const int n_wtiles = wtiles_m * wtiles_n;
+  const int WT = n_wtiles >= 2 ? 2 : 1;
+  const int ngroups = (n_wtiles + WT - 1) / WT;
   const int64_t nbatches = (nrows + 15) / 16;
+  int64_t groups = (int64_t)256 * 64 / ((int64_t)MT * NT * sizeof(T));
+  groups = groups < 256 ? 256 : (groups > 1024 ? 1024 : groups);
   const int chunks =
-      pick_chunks(ntiles, nbatches, (int64_t)ma * nb, P);
-#define SGM_GT(mt, nt)                                                      \
-  if (MT == mt && NT == nt) {                                               \
-    launch_gemm_tn<T, mt, nt>(Q, a0, ma, b0, nb, ncount, nbatches, tiles_n, \
-                              ntiles, chunks, P.buf, st);                   \
+      pick_chunks((int)groups, ngroups, nbatches, (int64_t)ma * nb, P);
+#define SGM_GT(mt, nt, wt)                                                  \
+  if (MT == mt && NT == nt && WT == wt) {                                   \
+    launch_gemm_tn<T, mt, nt, wt>(Q, a0, ma, b0, nb, ncount, nbatches,      \
+                                  wtiles_n, n_wtiles, ngroups, chunks,      \
+                                  P.buf, st);                               \
   } else
-  SGM_GT(1, 1) SGM_GT(2, 1) SGM_GT(4, 1) SGM_GT(8, 1)
-  SGM_GT(1, 2) SGM_GT(2, 2) SGM_GT(4, 2) SGM_GT(8, 2)
-  SGM_GT(1, 4) SGM_GT(2, 4) SGM_GT(4, 4)
+  SGM_GT(1, 1, 1) SGM_GT(2, 1, 1) SGM_GT(4, 1, 1) SGM_GT(8, 1, 1)
+  SGM_GT(1, 1, 2) SGM_GT(2, 1, 2) SGM_GT(4, 1, 2) SGM_GT(8, 1, 2)
+  SGM_GT(1, 2, 1) SGM_GT(2, 2, 1) SGM_GT(4, 2, 1) SGM_GT(8, 2, 1)
+  SGM_GT(1, 2, 2) SGM_GT(2, 2, 2) SGM_GT(4, 2, 2) SGM_GT(8, 2, 2)
+  SGM_GT(1, 4, 1) SGM_GT(2, 4, 1) SGM_GT(4, 4, 1)
+  SGM_GT(1, 4, 2) SGM_GT(2, 4, 2) SGM_GT(4, 4, 2)
   { throw Error{SGM_EINVAL, "gemm_tn: no kernel for this shape"}; }
 #undef SGM_GT
   launch_reduce(P.buf, chunks, ma, nb, C, ldc, 0, st);

@@ -42,7 +42,10 @@ def cols_of(t, n, ld, k):
 
 @pytest.mark.parametrize("mk", [lambda: W.conv_diff_2d(64, 10.0),
                                 lambda: W.poisson_3d(23),
-                                lambda: W.banded_problem(3001, band=300)[0]])
+                                lambda: W.banded_problem(3001, band=300)[0],
+                                # entries farther than 32767 from the
+                                # diagonal: 32-bit column indices
+                                lambda: W.banded_problem(70001, band=40000)[0]])
 def test_spmv_matches_csr_product(lib, mk):
     import torch
     A = mk()
@@ -273,6 +276,15 @@ def test_solve_jacobi_variable_coefficients(lib):
     b = W.rhs(A.n, 3)
     gpu, ref, rel = _compare_solve(lib, A, b, 16, 64, 1e-10, precond="jacobi")
     assert rel <= 1e-8
+
+
+def test_solve_wide_band_32bit_columns(lib):
+    """A matrix with entries up to 40000 from the diagonal keeps 32-bit
+    column indices in the matrix powers kernel and residual SpMV."""
+    A, b, _ = W.banded_problem(70001, seed=5, band=40000)
+    gpu, ref, rel = _compare_solve(lib, A, b, 16, 64, 1e-12)
+    assert rel <= 1e-10
+    assert list(gpu.s_hist) == ref.s_hist
 
 
 def test_solve_transpose(lib):
