@@ -30,21 +30,25 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
   if (s < nslices) {
     const int64_t base = ptr[s] + lane;
     const int w = width[s];
-    int k = 0;
-    for (; k + 4 <= w; k += 4) {
-      const int64_t e = base + (int64_t)k * kSlice;
-      const int32_t c0 = cb + col[e], c1 = cb + col[e + kSlice],
-                    c2 = cb + col[e + 2 * kSlice], c3 = cb + col[e + 3 * kSlice];
-      const T v0 = val[e], v1 = val[e + kSlice], v2 = val[e + 2 * kSlice],
-              v3 = val[e + 3 * kSlice];
-      sum += v0 * x[XV.row_off(c0)];
-      sum += v1 * x[XV.row_off(c1)];
-      sum += v2 * x[XV.row_off(c2)];
-      sum += v3 * x[XV.row_off(c3)];
-    }
-    for (; k < w; ++k) {
-      const int64_t e = base + (int64_t)k * kSlice;
-      sum += val[e] * x[XV.row_off(cb + col[e])];
+    // Eight entries per pass: all index and value loads of the pass go out
+    // together, then all eight x gathers.  Slots past the row's width
+    // re-read its last entry (a valid address) and weigh it by zero.
+    for (int k = 0; k < w; k += 8) {
+      int32_t c[8];
+      T v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int kk = min(k + q, w - 1);
+        const int64_t e = base + (int64_t)kk * kSlice;
+        c[q] = cb + col[e];
+        v[q] = val[e];
+      }
+      T xv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) xv[q] = x[XV.row_off(c[q])];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (k + q < w) sum += v[q] * xv[q];
     }
   }
   if constexpr (EPI == EPI_PLAIN) {
