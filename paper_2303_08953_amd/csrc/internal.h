@@ -219,6 +219,22 @@ template <typename T>
 void gemv_update(QView<const T> Q, const double* y, int k,
                  const double* sdev, double* x, int64_t n, hipStream_t st);
 
+// One-column blocks (s = 1), nrows a multiple of the 64-row panel:
+// C(0:ma) = Q(:, 0:ma)^T v with v = Q(:, vcol); pmask (device, may be
+// NULL): zero result when *pmask == 0.
+template <typename T>
+void col_dots(QView<const T> Q, int ma, int vcol, const int* pmask,
+              int64_t nrows, double* C, Partials& P, hipStream_t st);
+// v -= Q(:, 0:ma) w and *G = v^T v (pmask as above).
+template <typename T>
+void col_update(QView<T> Q, int ma, int vcol, const double* w,
+                const int* pmask, int64_t nrows, double* G, Partials& P,
+                hipStream_t st);
+// v *= *z when *pmask > 0.
+template <typename T>
+void col_scale(QView<T> Q, int vcol, const double* z, const int* pmask,
+               int64_t nrows, hipStream_t st);
+
 // ------------------------------------------------------------------ small FP64
 // Control block shared by the single-workgroup kernels of one block.
 enum Ctrl {

@@ -147,6 +147,23 @@ void orth_block(QView<T> Q, int64_t nrows, int nb, int s, double omega,
   const QView<const T> Qc = Q.template as<const T>();
   int* p1 = w.ctrl + C_P1;
   int* p2 = w.ctrl + C_P2;
+  if (s == 1) {
+    // one column: the same steps with column-wise kernels
+    col_dots<T>(Qc, nb, nb, nullptr, nrows, w.W, w.P, st);
+    col_update<T>(Q, nb, nb, w.W, nullptr, nrows, w.G, w.P, st);
+    pchol_ice(w.G, w.lds, 1, nullptr, omega, w.Z, w.Zinv, w.lds, p1,
+              w.pchol_scr, st);
+    col_scale<T>(Q, nb, w.Zinv, p1, nrows, st);
+    col_dots<T>(Qc, nb, nb, p1, nrows, w.R2, w.P, st);
+    col_update<T>(Q, nb, nb, w.R2, p1, nrows, w.G2, w.P, st);
+    pchol_ice(w.G2, w.lds, 1, p1, omega, w.Zt, w.Ztinv, w.lds, p2,
+              w.pchol_scr, st);
+    col_scale<T>(Q, nb, w.Ztinv, p2, nrows, st);
+    if (combine)
+      combine_r(w.W, w.ldw, w.R2, w.ldw, w.Z, w.Zt, w.lds, nb, w.ctrl, w.Rtop,
+                w.ldw, w.Rkk, w.lds, st);
+    return;
+  }
   // first BCGS: W = Q^T V; V -= Q W; G = V^T V
   gemm_tn<T>(Qc, 0, nb, nb, s, nullptr, nrows, w.W, w.ldw, w.P, st);
   update_gram<T>(Q, 0, nb, nb, s, w.W, w.ldw, nullptr, nrows, w.G, w.lds,

@@ -543,6 +543,126 @@ __global__ __launch_bounds__(256) void k_gemv_update(
   }
 }
 
+// ------------------------------------------------------------- s = 1
+// Column-wise kernels for one-column blocks (the Ritz pre-phase is a run
+// of them): MFMA tiles would waste 15 of their 16 columns, so these use
+// one row per lane.  Rows are taken in 64-row panels (one per wavefront
+// and step), so every column access of a wavefront is one contiguous
+// 64-element run.  Sums over rows are per-lane, then a fixed-order
+// shuffle tree, then a fixed-order sum over the four wavefronts, then a
+// fixed-order sum over workgroups (k_reduce_chunks): deterministic.
+
+// part[chunk][c] = sum over the chunk's rows of Q(r, c) v(r), c < ma, for
+// the CT-column tile ct of the grid, v = Q(:, vcol); with *pmask == 0 the
+// sums are zero.
+template <typename T, int CT>
+__global__ __launch_bounds__(kBlock) void k_col_dots(
+    QView<const T> Q, int ma, int vcol, const int* __restrict__ pmask,
+    int64_t npanels, int ctiles, int chunks, double* __restrict__ part) {
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int id = blockIdx.x;
+  const int xcd = id % 8, slot = id / 8;
+  const int ct = slot % ctiles;
+  const int chunk = (slot / ctiles) * 8 + xcd;
+  const int64_t p0 = npanels * chunk / chunks;
+  const int64_t p1 = npanels * (chunk + 1) / chunks;
+  const bool live = pmask == nullptr || *pmask > 0;
+  const int c0 = ct * CT;
+  T acc[CT];
+#pragma unroll
+  for (int j = 0; j < CT; ++j) acc[j] = (T)0;
+  if (live) {
+    int64_t oc[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j)
+      oc[j] = (int64_t)(c0 + j < ma ? c0 + j : 0) * Q.cstride;
+    for (int64_t pp = p0 + wave; pp < p1; pp += kBlock / kWave) {
+      const T* rb = Q.base + Q.row_off(pp * kPanel) + lane;
+      const T v = rb[(int64_t)vcol * Q.cstride];
+      T q[CT];
+#pragma unroll
+      for (int j = 0; j < CT; ++j) q[j] = rb[oc[j]];
+#pragma unroll
+      for (int j = 0; j < CT; ++j) acc[j] += q[j] * v;
+    }
+  }
+  __shared__ double red[kBlock / kWave][CT];
+#pragma unroll
+  for (int j = 0; j < CT; ++j) {
+    double t = (double)acc[j];
+    for (int off = kWave / 2; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (lane == 0) red[wave][j] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x < CT && c0 + (int)threadIdx.x < ma) {
+    const int j = threadIdx.x;
+    double t = red[0][j];
+    for (int w = 1; w < kBlock / kWave; ++w) t += red[w][j];
+    part[(int64_t)chunk * ma + c0 + j] = t;
+  }
+}
+
+// v = Q(:, vcol) -= Q(:, 0:ma) w (w float64, rounded to T like the MFMA
+// update stages it) and part[chunk] = sum of the new v(r)^2 over the
+// chunk's rows.  With *pmask == 0 nothing changes and the sums are zero.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_col_update(
+    QView<T> Q, int ma, int vcol, const double* __restrict__ w,
+    const int* __restrict__ pmask, int64_t npanels, int chunks,
+    double* __restrict__ part) {
+  extern __shared__ char smem_raw[];
+  T* ws = reinterpret_cast<T*>(smem_raw);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int id = blockIdx.x;
+  const int chunk = id;
+  const int64_t p0 = npanels * chunk / chunks;
+  const int64_t p1 = npanels * (chunk + 1) / chunks;
+  const bool live = pmask == nullptr || *pmask > 0;
+  for (int j = threadIdx.x; j < ma; j += kBlock) ws[j] = (T)w[j];
+  __syncthreads();
+  double ss = 0.0;
+  if (live) {
+    for (int64_t pp = p0 + wave; pp < p1; pp += kBlock / kWave) {
+      T* rb = Q.base + Q.row_off(pp * kPanel) + lane;
+      T v = rb[(int64_t)vcol * Q.cstride];
+      int j = 0;
+      for (; j + 8 <= ma; j += 8) {
+        T q[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) q[t] = rb[(int64_t)(j + t) * Q.cstride];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v -= q[t] * ws[j + t];
+      }
+      for (; j < ma; ++j) v -= rb[(int64_t)j * Q.cstride] * ws[j];
+      rb[(int64_t)vcol * Q.cstride] = v;
+      ss += (double)v * (double)v;
+    }
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
+  __shared__ double red[kBlock / kWave];
+  if (lane == 0) red[wave] = ss;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int k = 1; k < kBlock / kWave; ++k) t += red[k];
+    part[chunk] = t;
+  }
+}
+
+// v = Q(:, vcol) *= (T) *z when *pmask > 0.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_col_scale(
+    QView<T> Q, int vcol, const double* __restrict__ z,
+    const int* __restrict__ pmask, int64_t nrows) {
+  if (pmask != nullptr && *pmask <= 0) return;
+  const T zz = (T)z[0];
+  for (int64_t r = blockIdx.x * (int64_t)kBlock + threadIdx.x; r < nrows;
+       r += (int64_t)gridDim.x * kBlock) {
+    T* p = Q.at(r, vcol);
+    *p = *p * zz;
+  }
+}
+
 // ------------------------------------------------------------- dispatch
 // About two workgroups per CU (256 CUs): one full wave of workgroups, few
 // enough partials that their reduction stays cheap.
@@ -712,6 +832,61 @@ void gemv_update(QView<const T> Q, const double* y, int k,
   SGM_CHECK_LAUNCH();
 }
 
+namespace {
+// Row chunks of the column-wise kernels: about 1024 workgroups, at least
+// four panels (one per wavefront) each, a multiple of 8 for the XCD
+// decode, and within the partial-sum scratch.
+int col_chunks(int64_t npanels, int ctiles, int64_t per_chunk,
+               const Partials& P) {
+  int64_t c = 1024 / ctiles;
+  if (c > npanels / 4) c = npanels / 4;
+  if (per_chunk > 0 && c > P.cap / per_chunk) c = P.cap / per_chunk;
+  c = c / 8 * 8;
+  if (c < 8) c = 8;
+  if (c * per_chunk > P.cap)
+    throw Error{SGM_EINVAL, "partial-sum scratch too small for this block"};
+  return (int)c;
+}
+constexpr int kColTile = 16;
+}  // namespace
+
+template <typename T>
+void col_dots(QView<const T> Q, int ma, int vcol, const int* pmask,
+              int64_t nrows, double* C, Partials& P, hipStream_t st) {
+  if (ma <= 0) return;
+  const int64_t npanels = nrows / kPanel;
+  const int ctiles = (ma + kColTile - 1) / kColTile;
+  const int chunks = col_chunks(npanels, ctiles, ma, P);
+  hipLaunchKernelGGL((k_col_dots<T, kColTile>), dim3(chunks * ctiles),
+                     dim3(kBlock), 0, st, Q, ma, vcol, pmask, npanels, ctiles,
+                     chunks, P.buf);
+  SGM_CHECK_LAUNCH();
+  launch_reduce(P.buf, chunks, ma, 1, C, ma, 0, st);
+}
+
+template <typename T>
+void col_update(QView<T> Q, int ma, int vcol, const double* w,
+                const int* pmask, int64_t nrows, double* G, Partials& P,
+                hipStream_t st) {
+  const int64_t npanels = nrows / kPanel;
+  const int chunks = col_chunks(npanels, 1, 1, P);
+  const size_t lds = sizeof(T) * (size_t)(ma > 0 ? ma : 1);
+  hipLaunchKernelGGL(k_col_update<T>, dim3(chunks), dim3(kBlock), lds, st, Q,
+                     ma, vcol, w, pmask, npanels, chunks, P.buf);
+  SGM_CHECK_LAUNCH();
+  launch_reduce(P.buf, chunks, 1, 1, G, 1, 0, st);
+}
+
+template <typename T>
+void col_scale(QView<T> Q, int vcol, const double* z, const int* pmask,
+               int64_t nrows, hipStream_t st) {
+  int64_t grid = ceil_div(nrows, kBlock);
+  if (grid > 4096) grid = 4096;
+  hipLaunchKernelGGL(k_col_scale<T>, dim3((unsigned)grid), dim3(kBlock), 0, st,
+                     Q, vcol, z, pmask, nrows);
+  SGM_CHECK_LAUNCH();
+}
+
 #define SGM_INST(T)                                                          \
   template void gemm_tn<T>(QView<const T>, int, int, int, int, const int*,   \
                            int64_t, double*, int, Partials&, hipStream_t);   \
@@ -721,7 +896,13 @@ void gemv_update(QView<const T> Q, const double* y, int k,
   template void trsm_inv<T>(QView<T>, int, int, const double*, int,          \
                             const int*, int64_t, hipStream_t);               \
   template void gemv_update<T>(QView<const T>, const double*, int,           \
-                               const double*, double*, int64_t, hipStream_t);
+                               const double*, double*, int64_t, hipStream_t); \
+  template void col_dots<T>(QView<const T>, int, int, const int*, int64_t,   \
+                            double*, Partials&, hipStream_t);                \
+  template void col_update<T>(QView<T>, int, int, const double*, const int*, \
+                              int64_t, double*, Partials&, hipStream_t);     \
+  template void col_scale<T>(QView<T>, int, const double*, const int*,       \
+                             int64_t, hipStream_t);
 SGM_INST(double)
 SGM_INST(float)
 #undef SGM_INST
