@@ -251,13 +251,17 @@ void combine_r(const double* W, int ldw, const double* R2, int ldr2,
 // Per-block tail of the solver: combine_r, Hessenberg recovery, Givens
 // rotations and the convergence test in one single-workgroup kernel;
 // Rtop / Rkk (may be NULL) receive R(1:nb, k) (ld ldw) and R(k, k) (ld ldz).
+// res_out receives the per-column residual estimates and host_ctrl (may be
+// NULL) a copy of the control words; both may point into host memory
+// mapped for the device, so the host reads them without a copy.
 size_t block_tail_scratch_doubles(int nb_max, int s_max);
 void block_tail(const double* W, const double* R2, int ldw, const double* Z,
                 const double* Zt, const double* Zi, const double* Zti, int ldz,
                 int nb, int* ctrl, double* Rtop, double* Rkk, double* Hraw,
                 double* Hr, int ldh, double* cs, double* sn, double* g,
                 const double* rec, int n_rec, const double* beta0, double tol,
-                double* res_out, double* scratch, hipStream_t st);
+                double* res_out, int* host_ctrl, double* scratch,
+                hipStream_t st);
 void back_solve(const double* Hr, int ldh, const double* g, const int* kdev,
                 int kmax, double* y, hipStream_t st);
 void givens_init(double* g, int m, const double* beta, hipStream_t st);

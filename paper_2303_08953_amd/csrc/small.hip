@@ -332,7 +332,7 @@ __device__ __forceinline__ void tail_body(
     double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
     const double* __restrict__ rec, int n_rec,
     const double* __restrict__ beta0, double tol,
-    double* __restrict__ res_out) {
+    double* __restrict__ res_out, int* __restrict__ host_ctrl) {
   int& kdone_s = sh[0];
   int& conv_s = sh[1];
   int& bad_s = sh[2];
@@ -542,6 +542,9 @@ __device__ __forceinline__ void tail_body(
     ctrl[C_KDONE] = kdone;
     ctrl[C_CONV] = conv_s;
     ctrl[C_BAD] = bad_s;
+    // the control words the host needs, straight into its mapped memory
+    if (host_ctrl)
+      for (int k = 0; k < C_NCTRL; ++k) host_ctrl[k] = ctrl[k];
   }
 }
 
@@ -555,18 +558,18 @@ __global__ __launch_bounds__(kSmallBlock) void k_block_tail(
     double* __restrict__ sn, double* __restrict__ g,
     const double* __restrict__ rec, int n_rec,
     const double* __restrict__ beta0, double tol, double* __restrict__ res_out,
-    double* scratch) {
+    int* __restrict__ host_ctrl, double* scratch) {
   __shared__ double lds[kTailLds];
   __shared__ int sh[4];
   const int p = ctrl[C_P2] == 0 ? 1 : ctrl[C_P2];
   if (tail_doubles(nb, p) <= (size_t)kTailLds)
     tail_body(lds, sh, W, R2g, ldw, Zg, Ztg, Zig, Ztig, ldz, nb, ctrl,
               Rtop_out, Rkk_out, Hraw, Hr, ldh, cs, sn, g, rec, n_rec, beta0,
-              tol, res_out);
+              tol, res_out, host_ctrl);
   else
     tail_body(scratch, sh, W, R2g, ldw, Zg, Ztg, Zig, Ztig, ldz, nb, ctrl,
               Rtop_out, Rkk_out, Hraw, Hr, ldh, cs, sn, g, rec, n_rec, beta0,
-              tol, res_out);
+              tol, res_out, host_ctrl);
 }
 
 // y = Hr(0:k, 0:k)^{-1} g(0:k), column-oriented back substitution.
@@ -684,10 +687,12 @@ void block_tail(const double* W, const double* R2, int ldw, const double* Z,
                 int nb, int* ctrl, double* Rtop, double* Rkk, double* Hraw,
                 double* Hr, int ldh, double* cs, double* sn, double* g,
                 const double* rec, int n_rec, const double* beta0, double tol,
-                double* res_out, double* scratch, hipStream_t st) {
+                double* res_out, int* host_ctrl, double* scratch,
+                hipStream_t st) {
   hipLaunchKernelGGL(k_block_tail, dim3(1), dim3(kSmallBlock), 0, st, W, R2,
                      ldw, Z, Zt, Zi, Zti, ldz, nb, ctrl, Rtop, Rkk, Hraw, Hr,
-                     ldh, cs, sn, g, rec, n_rec, beta0, tol, res_out, scratch);
+                     ldh, cs, sn, g, rec, n_rec, beta0, tol, res_out,
+                     host_ctrl, scratch);
   SGM_CHECK_LAUNCH();
 }
 

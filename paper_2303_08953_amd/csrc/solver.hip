@@ -110,16 +110,34 @@ void layout(Arena& a, Work& w, int64_t n, int64_t sell_nnz, int m, int smax,
   w.info = a.take<int>(8);
 }
 
-// pinned host mirror for the per-block readback
+// Pinned host memory, mapped for the device and coherent: the block tail
+// writes the control words and residual estimates straight into it, and
+// the host reads them once the stream is idle (no copy kernels).
 struct HostMirror {
-  int* ctrl = nullptr;
+  int* ctrl = nullptr;      // host view
   double* res = nullptr;
   double* scal = nullptr;
+  int* dctrl = nullptr;     // device views of the same bytes
+  double* dres = nullptr;
 };
+
+// Wait for the stream by polling: a blocking synchronisation sleeps and
+// wakes up tens of microseconds late, once per block.
+void wait_stream(hipStream_t st) {
+  for (;;) {
+    const hipError_t e = hipStreamQuery(st);
+    if (e == hipSuccess) return;
+    if (e != hipErrorNotReady) {
+      (void)hipGetLastError();
+      throw Error{SGM_EHIP, std::string("stream: ") + hipGetErrorString(e)};
+    }
+  }
+}
 
 struct Handle {
   Matrix* M = nullptr;
-  void* pinned = nullptr;  // hipHostMalloc'd readback area
+  void* pinned = nullptr;      // hipHostMalloc'd readback area (host view)
+  void* pinned_dev = nullptr;  // the same memory as the device sees it
   size_t pinned_bytes = 0;
 };
 
@@ -260,7 +278,7 @@ struct Engine {
                            hipMemcpyHostToDevice, st));
     SGM_HIP(hipMemcpyAsync(w.wi, im.data(), sizeof(double) * ns,
                            hipMemcpyHostToDevice, st));
-    SGM_HIP(hipStreamSynchronize(st));
+    wait_stream(st);
     finish_shifts(ns, false);
   }
 
@@ -295,7 +313,7 @@ struct Engine {
     sh.rec.assign(3 * m0, 0.0);
     SGM_HIP(hipMemcpyAsync(sh.rec.data(), w.rec, sizeof(double) * 3 * m0,
                            hipMemcpyDeviceToHost, st));
-    SGM_HIP(hipStreamSynchronize(st));
+    wait_stream(st);
     if ((check_hqr && info[0] != 0) || info[3] != 0)
       throw Error{SGM_ENUMERIC, "Ritz values: QR iteration failed or "
                                 "non-finite values"};
@@ -330,13 +348,9 @@ struct Engine {
     SGM_HIP(hipEventRecord(ev[2], st));
     block_tail(w.W, w.R2, w.ldw, w.Z, w.Zt, w.Zinv, w.Ztinv, w.lds, nb,
                w.ctrl, nullptr, nullptr, w.Hraw, w.Hr, w.ldh, w.cs, w.sn, w.g,
-               rec, nrec, beta0, tol, w.res_blk, w.tail_scr, st);
+               rec, nrec, beta0, tol, hm.dres, hm.dctrl, w.tail_scr, st);
     SGM_HIP(hipEventRecord(ev[3], st));
-    SGM_HIP(hipMemcpyAsync(hm.ctrl, w.ctrl, sizeof(int) * C_NCTRL,
-                           hipMemcpyDeviceToHost, st));
-    SGM_HIP(hipMemcpyAsync(hm.res, w.res_blk, sizeof(double) * s_eff,
-                           hipMemcpyDeviceToHost, st));
-    SGM_HIP(hipStreamSynchronize(st));
+    wait_stream(st);
     float t01 = 0, t12 = 0, t23 = 0;
     SGM_HIP(hipEventElapsedTime(&t01, ev[0], ev[1]));
     SGM_HIP(hipEventElapsedTime(&t12, ev[1], ev[2]));
@@ -423,6 +437,8 @@ void run_solve(Handle* h, const double* b, const double* x0, double* x,
   hm.ctrl = static_cast<int*>(h->pinned);
   hm.res = reinterpret_cast<double*>(static_cast<char*>(h->pinned) + 256);
   hm.scal = reinterpret_cast<double*>(static_cast<char*>(h->pinned) + 128);
+  hm.dctrl = static_cast<int*>(h->pinned_dev);
+  hm.dres = reinterpret_cast<double*>(static_cast<char*>(h->pinned_dev) + 256);
   const double* v64 = S.val64;
   const float* v32 = S.val32;
   if (jac) {
@@ -461,12 +477,12 @@ void run_solve(Handle* h, const double* b, const double* x0, double* x,
   reduce_norm(w.P.buf, np, w.scal + 0, st);
   SGM_HIP(hipMemcpyAsync(hm.scal, w.scal, sizeof(double), hipMemcpyDeviceToHost,
                          st));
-  SGM_HIP(hipStreamSynchronize(st));
+  wait_stream(st);
   const double beta0 = hm.scal[0];
   R.t[0] = ms_since(t0);
   auto finish = [&]() {
     if (jac) vec_scale_div(x, A.diag, n, true, st);
-    SGM_HIP(hipStreamSynchronize(st));
+    wait_stream(st);
     R.t[7] = ms_since(t0);
   };
   if (beta0 == 0.0) {
@@ -489,7 +505,7 @@ void run_solve(Handle* h, const double* b, const double* x0, double* x,
     reduce_norm(w.P.buf, np2, w.scal + 1, st);
     SGM_HIP(hipMemcpyAsync(hm.scal + 1, w.scal + 1, sizeof(double),
                            hipMemcpyDeviceToHost, st));
-    SGM_HIP(hipStreamSynchronize(st));
+    wait_stream(st);
     R.t[5] += ms_since(tc);
     return hm.scal[1];
   };
@@ -676,8 +692,10 @@ sgm_status sgm_matrix_create(int64_t n, int64_t nnz, const int32_t* row_ptr,
   Handle* h = new Handle();
   try {
     h->M = matrix_create(n, nnz, row_ptr, col, val, as_stream(stream));
-    SGM_HIP(hipHostMalloc(&h->pinned, kPinnedBytes, hipHostMallocDefault));
+    SGM_HIP(hipHostMalloc(&h->pinned, kPinnedBytes,
+                          hipHostMallocMapped | hipHostMallocCoherent));
     h->pinned_bytes = kPinnedBytes;
+    SGM_HIP(hipHostGetDevicePointer(&h->pinned_dev, h->pinned, 0));
   } catch (...) {
     if (h->M) matrix_destroy(h->M);
     delete h;
