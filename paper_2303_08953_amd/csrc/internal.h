@@ -219,6 +219,15 @@ template <typename T>
 void gemv_update(QView<const T> Q, const double* y, int k,
                  const double* sdev, double* x, int64_t n, hipStream_t st);
 
+// Fused Q(:, b0:b0+p) = V Zinv (in place, p = min(nc, *pcount)) and
+// R2 (ka x nc, ld ldr) = Q(:, 0:ka)^T Q(:, b0:b0+p) (columns >= p zero).
+// Returns false (and does nothing) for shapes it does not cover (float32,
+// ka > 64, nc > 32 or nc < 2); the caller then runs trsm_inv + gemm_tn.
+template <typename T>
+bool trsm_proj(QView<T> Q, int ka, int b0, int nc, const double* Zinv,
+               int ldz, const int* pcount, int64_t nrows, double* R2, int ldr,
+               Partials& P, hipStream_t st);
+
 // One-column blocks (s = 1), nrows a multiple of the 64-row panel:
 // C(0:ma) = Q(:, 0:ma)^T v with v = Q(:, vcol); pmask (device, may be
 // NULL): zero result when *pmask == 0.

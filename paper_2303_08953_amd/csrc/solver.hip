@@ -189,9 +189,13 @@ void orth_block(QView<T> Q, int64_t nrows, int nb, int s, double omega,
   // first partial CholQR: p1, Z; V(:, 0:p1) = V Z^{-1}
   pchol_ice(w.G, w.lds, s, nullptr, omega, w.Z, w.Zinv, w.lds, p1,
             w.pchol_scr, st);
-  trsm_inv<T>(Q, nb, s, w.Zinv, w.lds, p1, nrows, st);
-  // second BCGS on the p1 accepted columns
-  gemm_tn<T>(Qc, 0, nb, nb, s, p1, nrows, w.R2, w.ldw, w.P, st);
+  // V(:, 0:p1) = V Zinv, then the second BCGS projection R2 = Q^T V on
+  // the p1 accepted columns (fused when the shape allows)
+  if (!trsm_proj<T>(Q, nb, nb, s, w.Zinv, w.lds, p1, nrows, w.R2, w.ldw, w.P,
+                    st)) {
+    trsm_inv<T>(Q, nb, s, w.Zinv, w.lds, p1, nrows, st);
+    gemm_tn<T>(Qc, 0, nb, nb, s, p1, nrows, w.R2, w.ldw, w.P, st);
+  }
   update_gram<T>(Q, 0, nb, nb, s, w.R2, w.ldw, p1, nrows, w.G2, w.lds, w.P,
                  st);
   // second partial CholQR: p2, Zt; V(:, 0:p2) = V Zt^{-1}
