@@ -6,7 +6,11 @@ s_max = 32, restart 128).
 
 One step = one float64 solve plus one float32-IR solve of that system to
 ||b - A x|| / ||b|| <= 1e-10, with the matrix analysed and every input
-already resident in HBM.  Prints ONE JSON line (see keys below).
+already resident in HBM; `value` is the float64 time with the column-wise
+Ritz pre-phase.  The same two solves with the pre-phase in adaptive
+monomial-basis blocks are timed too and reported beside it
+(fp64_monomial_prephase, fp32_ir_monomial_prephase).  Prints ONE JSON line
+(see keys below).
 
 Roofline: the dominant kernel is the SELL SpMV of the matrix powers kernel
 (float64).  Its average launch duration comes from the HIP event pair the
@@ -89,8 +93,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nx", type=int, default=128)
-    ap.add_argument("--mode", choices=["both", "fp64", "fp32_ir"],
-                    default="both")
+    ap.add_argument("--mode", choices=["both", "fp64", "fp32_ir", "all"],
+                    default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="run one plain device copy of this size (for the "
@@ -119,7 +123,12 @@ def main():
     ws = sgm.Workspace()
     o64 = dict(s_max=s_max, restart=restart, tol=tol, max_restarts=1000)
     o32 = dict(o64, precision="fp32_ir", inner_tol=1e-6, max_outer=500)
-    modes = {"both": [("fp64", o64), ("fp32_ir", o32)],
+    o64m = dict(o64, prephase="monomial", prephase_s=8)
+    o32m = dict(o32, prephase="monomial", prephase_s=8)
+    both = [("fp64", o64), ("fp32_ir", o32)]
+    modes = {"both": both,
+             "all": both + [("fp64_monomial_prephase", o64m),
+                            ("fp32_ir_monomial_prephase", o32m)],
              "fp64": [("fp64", o64)], "fp32_ir": [("fp32_ir", o32)]}[args.mode]
 
     if args.calibrate_copy_mb > 0:
@@ -196,6 +205,10 @@ def main():
     if "fp64" in per and "fp32_ir" in per:
         out["fp32_ir"]["speedup_vs_fp64"] = round(
             out["fp64"]["ms"] / out["fp32_ir"]["ms"], 3)
+    for name in ("fp64_monomial_prephase", "fp32_ir_monomial_prephase"):
+        if name in per and "fp64" in per:
+            out[name]["speedup_vs_fp64"] = round(
+                out["fp64"]["ms"] / out[name]["ms"], 3)
 
     # roofline of the dominant kernel: float64 MPK SpMV
     rs = infos[primary]

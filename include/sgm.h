@@ -53,6 +53,11 @@ typedef enum {
 typedef enum { SGM_PRECOND_NONE = 0, SGM_PRECOND_JACOBI = 1 } sgm_precond;
 
 typedef enum {
+  SGM_PREPHASE_CGS2 = 0,     /* one column per step (column-wise Arnoldi)  */
+  SGM_PREPHASE_MONOMIAL = 1  /* adaptive monomial-basis s-step blocks      */
+} sgm_prephase;
+
+typedef enum {
   SGM_FP64 = 0,    /* everything in double precision                        */
   SGM_FP32_IR = 1  /* float32 inner s-step cycles inside float64 refinement */
 } sgm_precision;
@@ -114,11 +119,21 @@ typedef struct {
   const double* shifts_host; /* optional (host) Ritz values as (re, im)
                              pairs; when given, the pre-phase is skipped     */
   int32_t n_shifts;       /* number of (re, im) pairs in shifts_host         */
+  sgm_prephase prephase;  /* how the Ritz pre-phase builds its m0 columns:
+                             SGM_PREPHASE_CGS2 (default) one column per step
+                             (column-wise CGS2 Arnoldi, Sec. 3.4);
+                             SGM_PREPHASE_MONOMIAL in monomial-basis blocks
+                             of Alg. 4 with partial CholQR adapting their
+                             size (same Krylov space and Hessenberg matrix,
+                             block-wise passes over the basis)            */
+  int32_t prephase_s;     /* first block size of the monomial pre-phase
+                             (default 8); >= 1                               */
 } sgm_opts;
 
 /* Fills *o (host) with the defaults: s_max 8, restart 64, max_restarts 100,
  * tol 1e-10, no preconditioner, scaled Newton, FP64, omega/omega_est rule,
- * estimator on, inner_tol 1e-6, max_outer 200, ritz_reuse 1. */
+ * estimator on, inner_tol 1e-6, max_outer 200, ritz_reuse 1, column-wise
+ * pre-phase, prephase_s 8. */
 void sgm_opts_default(sgm_opts* o);
 
 typedef struct {

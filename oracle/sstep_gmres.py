@@ -492,6 +492,8 @@ class Options:
     use_estimator: bool = True
     ritz_reuse: bool = True
     shifts: object = None             # optional complex Ritz values (skip pre-phase)
+    prephase: str = "cgs2"            # "cgs2": s = 1 steps; "monomial": s-step blocks
+    prephase_s: int = 8               # first block size of the monomial pre-phase
     cond: str = "ice"                 # "ice" | "svd"
     work_dtype: object = np.float64   # float32 => single-precision inner model
     record: bool = False              # keep per-block traces for tests
@@ -582,9 +584,13 @@ class _Engine:
         """One restart cycle of Alg. 4 from the residual r (||r|| = beta).
 
         When the shifts are not known yet, the first m0 = min(s_max, m)
-        columns are built with s = 1 and the monomial basis -- the s = 1
-        case of Alg. 4, i.e. column-wise CGS2 Arnoldi (Sec. 3.3) -- and the
-        shifts are derived from them before the s-step blocks continue.
+        columns are built with the monomial basis -- by default with s = 1,
+        the s = 1 case of Alg. 4, i.e. column-wise CGS2 Arnoldi (Sec. 3.3);
+        with prephase="monomial" in blocks of Alg. 4 itself, starting at
+        prephase_s and adapting (non-increasing) like any block, the last
+        one cut to end at exactly m0 columns -- and the shifts are derived
+        from them before the scaled Newton blocks continue.  Both build the
+        same Krylov space and Hessenberg matrix (up to rounding).
         Returns (dx, k, converged): the update Q(:, 1:k) y of this cycle.
         """
         o = self.o
@@ -599,13 +605,17 @@ class _Engine:
         tol = -1.0 if prephase_only else o.tol
         nb, k, conv = 1, 0, False
         s = st.s_init
+        s_pre = max(1, min(o.prephase_s, m0)) if o.prephase == "monomial" else 1
         while nb <= last and not conv:
             if st.shifts is None and nb > m0:
                 self.finish_prephase(Hraw, nb - 1, st)
                 s = st.s_init
             in_pre = st.shifts is None
             sh = mono if in_pre else st.shifts
-            s_eff = min(1 if in_pre else s, m + 1 - nb)
+            if in_pre:
+                s_eff = min(s_pre, m0 + 1 - nb, m + 1 - nb)
+            else:
+                s_eff = min(s, m + 1 - nb)
             V = self.mpk(Q[:, nb - 1], sh, s_eff)
             bq = block_orth(Q, nb, V, self.omega, self.wd, o.cond)
             if trace is not None and not in_pre and "first_block" not in trace:
@@ -642,6 +652,8 @@ class _Engine:
             nb += p
             if not in_pre:
                 s = p                  # Alg. 4: the step size never grows
+            elif o.prephase == "monomial":
+                s_pre = p
         if st.shifts is None:
             self.finish_prephase(Hraw, k, st)
         if trace is not None and "H_first_cycle" not in trace and not prephase_only:

@@ -25,6 +25,7 @@ OK, NOT_CONVERGED, EINVAL, EHIP, ENOMEM, ENUMERIC = 0, 1, -1, -2, -3, -4
 BASIS = {"scaled_newton": 0, "newton": 1, "monomial": 2}
 PRECOND = {"none": 0, "jacobi": 1}
 PRECISION = {"fp64": 0, "fp32_ir": 1}
+PREPHASE = {"cgs2": 0, "monomial": 1}
 
 
 class SgmError(RuntimeError):
@@ -43,6 +44,7 @@ class Opts(C.Structure):
         ("inner_tol", C.c_double), ("max_outer", C.c_int32),
         ("ritz_reuse", C.c_int32),
         ("shifts_host", C.POINTER(C.c_double)), ("n_shifts", C.c_int32),
+        ("prephase", C.c_int), ("prephase_s", C.c_int32),
     ]
 
 
@@ -213,7 +215,8 @@ class Matrix:
 def make_opts(s_max=8, restart=64, max_restarts=100, tol=1e-10,
               precond="none", basis="scaled_newton", precision="fp64",
               omega=0.0, omega_est=0.0, use_estimator=True, transpose=False,
-              inner_tol=1e-6, max_outer=200, ritz_reuse=True, shifts=None):
+              inner_tol=1e-6, max_outer=200, ritz_reuse=True, shifts=None,
+              prephase="cgs2", prephase_s=8):
     o = Opts()
     lib().sgm_opts_default(C.byref(o))
     o.s_max, o.restart, o.max_restarts, o.tol = s_max, restart, max_restarts, tol
@@ -225,6 +228,8 @@ def make_opts(s_max=8, restart=64, max_restarts=100, tol=1e-10,
     o.transpose = int(bool(transpose))
     o.inner_tol, o.max_outer = inner_tol, max_outer
     o.ritz_reuse = int(bool(ritz_reuse))
+    o.prephase = PREPHASE[prephase]
+    o.prephase_s = int(prephase_s)
     keep = None
     if shifts is not None:
         z = np.asarray(shifts, dtype=np.complex128).ravel()

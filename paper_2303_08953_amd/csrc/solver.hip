@@ -387,6 +387,10 @@ struct Engine {
     int nb = 1, k = 0;
     bool conv = false;
     int s = sh.s_init;
+    // pre-phase block size: 1 (column-wise), or adaptive monomial blocks
+    int s_pre = o.prephase == SGM_PREPHASE_MONOMIAL
+                    ? std::max(1, std::min(o.prephase_s, std::max(m0, 1)))
+                    : 1;
     auto t_pre = Clock::now();
     bool timing_pre = !sh.known;
     while (nb <= last && !conv) {
@@ -397,7 +401,9 @@ struct Engine {
         timing_pre = false;
       }
       const bool in_pre = !sh.known;
-      const int s_eff = std::min(in_pre ? 1 : s, m + 1 - nb);
+      const int s_eff = in_pre ? std::min(std::min(s_pre, m0 + 1 - nb),
+                                          m + 1 - nb)
+                               : std::min(s, m + 1 - nb);
       BlockOut b = block(nb, s_eff, in_pre || o.basis == SGM_BASIS_MONOMIAL,
                          beta0_dev, prephase_only ? -1.0 : tol);
       if (b.bad) throw Error{SGM_ENUMERIC, "non-finite residual estimate"};
@@ -415,6 +421,7 @@ struct Engine {
       if (b.conv) conv = true;
       nb += b.p2;
       if (!in_pre) s = b.p2;
+      else if (o.prephase == SGM_PREPHASE_MONOMIAL) s_pre = b.p2;
     }
     if (!sh.known) {
       compute_shifts(k);
@@ -629,6 +636,10 @@ void validate_opts(const sgm_opts* o) {
   if (o->shifts_host != nullptr)
     SGM_REQUIRE(o->n_shifts >= 1 && o->n_shifts <= 1024,
                 "n_shifts must be in [1, 1024]");
+  SGM_REQUIRE(o->prephase == SGM_PREPHASE_CGS2 ||
+                  o->prephase == SGM_PREPHASE_MONOMIAL,
+              "unknown prephase");
+  SGM_REQUIRE(o->prephase_s >= 1, "prephase_s must be >= 1");
 }
 
 int nshift_max(const sgm_opts& o) {
@@ -780,6 +791,8 @@ void sgm_opts_default(sgm_opts* o) {
   o->ritz_reuse = 1;
   o->shifts_host = nullptr;
   o->n_shifts = 0;
+  o->prephase = SGM_PREPHASE_CGS2;
+  o->prephase_s = 8;
 }
 
 sgm_status sgm_workspace_size(sgm_matrix A, const sgm_opts* o,

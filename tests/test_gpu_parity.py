@@ -249,6 +249,24 @@ def test_solve_ragged_poisson_restarts_x0(lib):
     assert gpu.info["restarts"] >= 1
 
 
+@pytest.mark.parametrize("mk,s_max,restart", [
+    (lambda: W.conv_diff_2d(64, 10.0), 8, 64),
+    (lambda: W.poisson_3d(27), 32, 96)])
+def test_solve_monomial_prephase(lib, mk, s_max, restart):
+    """Ritz pre-phase in adaptive monomial-basis blocks (prephase
+    "monomial"): the same blocks, residual history and solution as the
+    oracle with the same option."""
+    A = mk()
+    b = W.rhs(A.n, 1)
+    gpu, ref, rel = _compare_solve(lib, A, b, s_max, restart, 1e-10,
+                                   prephase="monomial", prephase_s=8)
+    assert rel <= 1e-8
+    assert list(gpu.s_hist) == ref.s_hist
+    assert ref.s_hist[0] > 1
+    h, hr = np.array(gpu.res_hist), np.array(ref.res_hist)
+    assert np.all(np.abs(h - hr) <= 1e-6 * hr + 1e-13)
+
+
 def test_solve_no_ritz_reuse_and_no_estimator(lib):
     A = W.conv_diff_2d(32, 10.0)
     b = W.rhs(A.n, 5)

@@ -546,3 +546,33 @@ def test_happy_breakdown_eigenvector_rhs():
                                          basis=basis))
         assert r.status == "ok" and r.iters == 1
         assert np.allclose(r.x, b / lam, rtol=1e-15, atol=0)
+
+
+def test_monomial_prephase_matches_columnwise_prephase():
+    """The monomial s-step pre-phase builds the same Krylov space and
+    Hessenberg matrix as the column-wise CGS2 one (which the MGS-GMRES pin
+    fixes): same Ritz values, same first-cycle residual history and
+    solution, in blocks that adapt below prephase_s."""
+    A = W.poisson_3d(16)
+    M = csr(A)
+    b = W.rhs(A.n, 2)
+    kw = dict(s_max=24, restart=48, tol=1e-10, max_restarts=50)
+    ra = o.solve(M, b, opts=o.Options(**kw))
+    rb = o.solve(M, b, opts=o.Options(prephase="monomial", prephase_s=8, **kw))
+    m0 = 24
+    assert ra.s_hist[:m0] == [1] * m0
+    pre = []
+    tot = 0
+    for p in rb.s_hist:
+        pre.append(p)
+        tot += p
+        if tot >= m0:
+            break
+    assert tot == m0 and 1 < max(pre) <= 8 and len(pre) < m0
+    za = np.sort_complex(ra.shifts.ritz)
+    zb = np.sort_complex(rb.shifts.ritz)
+    assert np.abs(za - zb).max() <= 1e-8 * np.abs(za).max()
+    ha, hb = np.array(ra.res_hist[:m0]), np.array(rb.res_hist[:m0])
+    assert np.all(np.abs(ha - hb) <= 1e-8 * ha)
+    assert ra.iters == rb.iters
+    assert np.linalg.norm(ra.x - rb.x) <= 1e-10 * np.linalg.norm(ra.x)
