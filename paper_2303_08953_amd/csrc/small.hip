@@ -44,55 +44,46 @@ __device__ void top_eig_2x2(double a, double b, double c, double& lam,
 // for every later column k: when row j of R appears, P_k <- s1 P_k +
 // c1 R(j, k) and Q_k <- s2 Q_k + d_j R(j, k), which is exactly
 // y^T R(0:j+1, k) and d^T R(0:j+1, k) after the update y <- [s1 y; c1],
-// d <- [s2 d; d_j].  No reductions are needed: the owner of column j + 1
-// publishes (P, Q) for the next step.
-// Each step: (1) every thread evaluates the pivot and the estimator
-// (uniform), (2) the owners scale row j and publish it to rowj[], (3) all
-// threads apply the rank-1 trailing update, one element per lane: lane
-// (wave w, lane l) updates column j+1+l (+64 ...) at rows j+1+w, j+1+w+nw,
-// ... so row j's entries come from rowj[] as broadcasts.
+// d <- [s2 d; d_j].  No reductions are needed.
+// Pipeline of step j (several wavefronts):
+//   (a) every thread reads the published estimator step of column j
+//       (pivot root, its reciprocal, the two rotations, d_j, stop flag);
+//   (b) the owners scale row j into rowj[], update their running sums, and
+//       the owner of column j + 1 publishes (P, Q) and its next pivot
+//       A(j+1, j+1) - R(j, j+1)^2;
+//   (c) wavefront 0 evaluates the estimator step of column j + 1 while the
+//       other wavefronts apply the rank-1 trailing update of row j.
+// With one wavefront, (c) runs the estimator step and then the update.
 // The factorisation stops before a column whose pivot is not positive and
 // finite or whose estimate exceeds omega.  Outputs: p, R (p x p upper),
-// Rinv = R^{-1} (explicit, column-wise back substitution in LDS), both
-// column-major with leading dimension ldr.
+// Rinv = R^{-1}, both column-major with leading dimension ldr.
 constexpr int kPcholLds = 140 * 1024 / 8;
 constexpr int kPcholMaxS = 256;
 
-// The body is instantiated twice: with the LDS array (every access then
-// compiles to a ds_* instruction) and with global scratch for large s.
-__device__ __forceinline__ void pchol_body(
-    double* Aw, double* rowj, double (*bc)[2], const double* __restrict__ G,
-    int ldg, int s, double omega, double* __restrict__ R,
-    double* __restrict__ Rinv, int ldr, int* p_out) {
-  const int tid = threadIdx.x;
-  const int nthr = blockDim.x;
-  const int lane = tid % kWave, wave = tid / kWave, nw = nthr / kWave;
-  const int la = s > 0 ? s : 1;
-  double* Ri = Aw + (size_t)s * s;
-  for (int e = tid; e < s * s; e += nthr) {
-    const int i = e % s, j = e / s;  // G symmetric: (i, j) -> row i, col j
-    Aw[i * la + j] = G[(int64_t)j * ldg + i];
-  }
-  double P = 0.0, Q = 0.0;  // estimator sums of column tid
-  double smax2 = 0.0, dn2 = 0.0;  // uniform estimator state
-  int p = s;
-  __syncthreads();
-  for (int j = 0; j < s; ++j) {
-    // (1) pivot and estimator, evaluated identically by every thread
-    const double piv = Aw[j * la + j];
-    if (!(piv > 0.0) || !isfinite(piv)) { p = j; break; }
-    const double rjj = sqrt(piv);
-    const double rinv = 1.0 / rjj;
-    double s1 = 0.0, c1 = 1.0, s2 = 0.0, c2 = 1.0, kappa = 1.0, a2 = 0.0;
+// Estimator step of column j (all lanes of the calling wavefront): from the
+// pivot and the running sums of column j, update (smax2, dn2) and publish
+// the step in est[0..7]: rjj, 1/rjj, s1, c1, s2, c2, d_j, stop (0/1).
+__device__ __forceinline__ void ice_step(int j, double piv, double a,
+                                         double a2, double omega,
+                                         double& smax2, double& dn2,
+                                         double* est) {
+  const int lane = threadIdx.x % kWave;
+  double stop = 0.0;
+  double rjj = 0.0, rinv = 0.0, s1 = 0.0, c1 = 1.0, s2 = 0.0, c2 = 1.0;
+  double dj = 0.0;
+  if (!(piv > 0.0) || !isfinite(piv)) {
+    stop = 1.0;
+  } else {
+    rjj = sqrt(piv);
+    rinv = 1.0 / rjj;
+    double kappa = 1.0;
     const double r2 = rjj * rjj;
     if (j == 0) {
       smax2 = r2;
       dn2 = rinv * rinv;
     } else {
-      // the two 2x2 eigenproblems (largest and smallest singular value)
-      // run side by side: even lanes take the first, odd lanes the second
-      const double a = bc[j & 1][0];
-      a2 = bc[j & 1][1];
+      // the two 2x2 eigenproblems side by side: even lanes take the
+      // largest singular value, odd lanes the smallest
       const bool second = lane & 1;
       const double ar = a2 * rinv;
       const double ea = second ? dn2 + ar * ar : smax2 + a * a;
@@ -108,10 +99,73 @@ __device__ __forceinline__ void pchol_body(
       c2 = readlane_f64(v, 1);
       kappa = sqrt(smax2 * dn2);
     }
-    if (!(kappa <= omega)) { p = j; break; }
-    const double dj = (c2 - s2 * a2) * rinv;
-    // (2) row j of R, the owners' running estimator sums, and (P, Q) of
-    // column j + 1 for the next step
+    if (!(kappa <= omega)) stop = 1.0;
+    dj = (c2 - s2 * a2) * rinv;
+  }
+  if (lane == 0) {
+    est[0] = rjj;
+    est[1] = rinv;
+    est[2] = s1;
+    est[3] = c1;
+    est[4] = s2;
+    est[5] = c2;
+    est[6] = dj;
+    est[7] = stop;
+  }
+}
+
+// The body is instantiated twice: with the LDS array (every access then
+// compiles to a ds_* instruction) and with global scratch for large s.
+__device__ __forceinline__ void pchol_body(
+    double* Aw, double* rowj, double (*bc)[3], double (*est)[8],
+    const double* __restrict__ G, int ldg, int s, double omega,
+    double* __restrict__ R, double* __restrict__ Rinv, int ldr, int* p_out) {
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  const int lane = tid % kWave, wave = tid / kWave, nw = nthr / kWave;
+  const int la = s > 0 ? s : 1;
+  // Rinv rows padded to an odd stride: the column sweep below has each
+  // thread walk its own row, and an even stride would put all of them in
+  // one LDS bank
+  const int lri = s + 1;
+  double* Ri = Aw + (size_t)s * s;
+  for (int e = tid; e < s * s; e += nthr) {
+    const int i = e % s, j = e / s;  // G symmetric: (i, j) -> row i, col j
+    Aw[i * la + j] = G[(int64_t)j * ldg + i];
+  }
+  double P = 0.0, Q = 0.0;        // estimator sums of column tid
+  double smax2 = 0.0, dn2 = 0.0;  // estimator state (wavefront 0)
+  int p = s;
+  __syncthreads();
+  if (s > 0 && wave == 0)
+    ice_step(0, Aw[0], 0.0, 0.0, omega, smax2, dn2, est[0]);
+  __syncthreads();
+  // trailing update of row j over the given wavefronts
+  auto trail = [&](int j, int w0, int nwu) {
+    for (int k = j + 1 + lane; k < s; k += kWave) {
+      const double rk = rowj[k];
+      int l = j + 1 + (wave - w0);
+      for (; l + 3 * nwu <= k; l += 4 * nwu) {
+        double* a = Aw + (size_t)l * la + k;
+        const size_t st = (size_t)nwu * la;
+        const double a0 = a[0], a1 = a[st], a2 = a[2 * st], a3 = a[3 * st];
+        const double r0 = rowj[l], r1 = rowj[l + nwu], r2 = rowj[l + 2 * nwu],
+                     r3 = rowj[l + 3 * nwu];
+        a[0] = a0 - r0 * rk;
+        a[st] = a1 - r1 * rk;
+        a[2 * st] = a2 - r2 * rk;
+        a[3 * st] = a3 - r3 * rk;
+      }
+      for (; l <= k; l += nwu) Aw[(size_t)l * la + k] -= rowj[l] * rk;
+    }
+  };
+  for (int j = 0; j < s; ++j) {
+    // (a) the estimator step of column j
+    const double* e = est[j & 1];
+    if (e[7] != 0.0) { p = j; break; }
+    const double rjj = e[0], rinv = e[1], s1 = e[2], c1 = e[3], s2 = e[4],
+                 dj = e[6];
+    // (b) row j of R, the running sums, and what the next step needs
     if (tid > j && tid < s) {
       const double rjk = Aw[j * la + tid] * rinv;
       Aw[j * la + tid] = rjk;
@@ -121,55 +175,69 @@ __device__ __forceinline__ void pchol_body(
       if (tid == j + 1) {
         bc[(j + 1) & 1][0] = P;
         bc[(j + 1) & 1][1] = Q;
+        bc[(j + 1) & 1][2] = Aw[(j + 1) * la + j + 1] - rjk * rjk;
       }
     }
     if (tid == j) Aw[j * la + j] = rjj;
     __syncthreads();
-    // (3) trailing update A(l, k) -= R(j, l) R(j, k), j < l <= k < s; the
-    // loads of four rows are issued before their stores
-    for (int k = j + 1 + lane; k < s; k += kWave) {
-      const double rk = rowj[k];
-      int l = j + 1 + wave;
-      for (; l + 3 * nw <= k; l += 4 * nw) {
-        double* a = Aw + (size_t)l * la + k;
-        const size_t st = (size_t)nw * la;
-        const double a0 = a[0], a1 = a[st], a2 = a[2 * st], a3 = a[3 * st];
-        const double r0 = rowj[l], r1 = rowj[l + nw], r2 = rowj[l + 2 * nw],
-                     r3 = rowj[l + 3 * nw];
-        a[0] = a0 - r0 * rk;
-        a[st] = a1 - r1 * rk;
-        a[2 * st] = a2 - r2 * rk;
-        a[3 * st] = a3 - r3 * rk;
+    // (c) next estimator step beside the trailing update
+    const bool more = j + 1 < s;
+    if (nw == 1) {
+      if (more) {
+        const double* b = bc[(j + 1) & 1];
+        ice_step(j + 1, b[2], b[0], b[1], omega, smax2, dn2,
+                 est[(j + 1) & 1]);
       }
-      for (; l <= k; l += nw) Aw[(size_t)l * la + k] -= rowj[l] * rk;
+      trail(j, 0, 1);
+    } else if (wave == 0) {
+      if (more) {
+        const double* b = bc[(j + 1) & 1];
+        ice_step(j + 1, b[2], b[0], b[1], omega, smax2, dn2,
+                 est[(j + 1) & 1]);
+      }
+    } else {
+      trail(j, 1, nw - 1);
     }
     __syncthreads();
   }
   if (tid == 0) *p_out = p;
-  // Rinv = R^{-1}: thread c owns column c (back substitution R x = e_c)
-  // with the diagonal reciprocals formed first, in parallel
-  for (int c = tid; c < p; c += nthr) rowj[c] = 1.0 / Aw[c * la + c];
+  // Rinv by recursive doubling: the diagonal holds 1 / R(i, i); at level b
+  // neighbouring inverted diagonal blocks A^{-1} (rows a0..a0+b) and
+  // C^{-1} (rows c0 = a0+b ..) of the factor [A B; 0 C] are joined through
+  // the off-diagonal block -A^{-1} (B C^{-1}): two products, every output
+  // in parallel, log2(p) levels.  T = B C^{-1} is kept, transposed, in the
+  // unused lower triangle of the same block pair.
+  for (int i = tid; i < p; i += nthr) Ri[i * lri + i] = 1.0 / Aw[i * la + i];
   __syncthreads();
-  for (int c = tid; c < p; c += nthr) {
-    Ri[c * la + c] = rowj[c];
-    for (int r = c - 1; r >= 0; --r) {
-      const double* ar = Aw + r * la;
-      double acc0 = 0.0, acc1 = 0.0;
-      int t = r + 1;
-      for (; t + 1 <= c; t += 2) {
-        acc0 += ar[t] * Ri[t * la + c];
-        acc1 += ar[t + 1] * Ri[(t + 1) * la + c];
-      }
-      if (t <= c) acc0 += ar[t] * Ri[t * la + c];
-      Ri[r * la + c] = -(acc0 + acc1) * rowj[r];
+  for (int b = 1; b < p; b *= 2) {
+    const int npairs = (p + 2 * b - 1) / (2 * b);
+    const int items = npairs * b * b;
+    for (int e = tid; e < items; e += nthr) {   // T = B C^{-1}
+      const int q = e / (b * b), i = (e % (b * b)) / b, j = e % b;
+      const int a0 = 2 * q * b, c0 = a0 + b;
+      if (c0 + j >= p) continue;
+      double acc = 0.0;
+      for (int t = 0; t <= j; ++t)
+        acc += Aw[(a0 + i) * la + c0 + t] * Ri[(c0 + t) * lri + c0 + j];
+      Ri[(c0 + j) * lri + a0 + i] = acc;  // transposed, lower triangle
     }
+    __syncthreads();
+    for (int e = tid; e < items; e += nthr) {   // X = -A^{-1} T
+      const int q = e / (b * b), i = (e % (b * b)) / b, j = e % b;
+      const int a0 = 2 * q * b, c0 = a0 + b;
+      if (c0 + j >= p) continue;
+      double acc = 0.0;
+      for (int t = i; t < b; ++t)
+        acc += Ri[(a0 + i) * lri + a0 + t] * Ri[(c0 + j) * lri + a0 + t];
+      Ri[(a0 + i) * lri + c0 + j] = -acc;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   for (int e = tid; e < p * p; e += nthr) {
     const int i = e % p, j = e / p;
     const bool up = i <= j;
     R[(int64_t)j * ldr + i] = up ? Aw[i * la + j] : 0.0;
-    Rinv[(int64_t)j * ldr + i] = up ? Ri[i * la + j] : 0.0;
+    Rinv[(int64_t)j * ldr + i] = up ? Ri[i * lri + j] : 0.0;
   }
 }
 
@@ -179,14 +247,15 @@ __global__ __launch_bounds__(kSmallBlock) void k_pchol(
     int* p_out, double* scratch) {
   __shared__ double buf[kPcholLds];
   __shared__ double rowj[kPcholMaxS];
-  __shared__ double bc[2][2];
+  __shared__ double bc[2][3];
+  __shared__ double est[2][8];
   int s = smax;
   if (s_dev) s = min(s, *s_dev);
-  // work layout: A (s x s, row-major) | Rinv (s x s, row-major)
-  if (2 * (size_t)s * s <= (size_t)kPcholLds)
-    pchol_body(buf, rowj, bc, G, ldg, s, omega, R, Rinv, ldr, p_out);
+  // work layout: A (s x s, row-major) | Rinv (s x (s + 1), row-major)
+  if ((size_t)s * (2 * s + 1) <= (size_t)kPcholLds)
+    pchol_body(buf, rowj, bc, est, G, ldg, s, omega, R, Rinv, ldr, p_out);
   else
-    pchol_body(scratch, rowj, bc, G, ldg, s, omega, R, Rinv, ldr, p_out);
+    pchol_body(scratch, rowj, bc, est, G, ldg, s, omega, R, Rinv, ldr, p_out);
 }
 
 // Combine both BCGS passes (Alg. 4): R(1:i, k) = W(:, 1:p) + R2(:, 1:p) Z,
