@@ -220,8 +220,9 @@ def main():
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     khash = spmv_source_hash()
     out["roofline"] = {
-        "kernel": f"k_spmv<{'double' if vb == 8 else 'float'}, EPI_MPK> "
-                  "(SELL-C-64 SpMV of the matrix powers kernel)",
+        "kernel": f"k_spmv<{'double' if vb == 8 else 'float'}, EPI_MPK, "
+                  "int16_t> (SELL-C-64 SpMV of the matrix powers kernel, "
+                  "16-bit column deltas; achieved is on the CSR bytes)",
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": load_traffic(khash),
