@@ -58,6 +58,16 @@ typedef enum {
 } sgm_prephase;
 
 typedef enum {
+  SGM_ORTH_BCGS2 = 0,      /* Alg. 4: both BCGS passes take their Gram
+                              matrix from the updated block               */
+  SGM_ORTH_BCGS2_PYTH = 1  /* second pass takes it by Pythagoras,
+                              G2 = Q1^T Q1 - R2^T R2 (Q1 = first-pass
+                              block, R2 = its projection), so the second
+                              update and triangular solve are one pass
+                              over the block (not in the paper)           */
+} sgm_orth;
+
+typedef enum {
   SGM_FP64 = 0,    /* everything in double precision                        */
   SGM_FP32_IR = 1  /* float32 inner s-step cycles inside float64 refinement */
 } sgm_precision;
@@ -128,12 +138,15 @@ typedef struct {
                              block-wise passes over the basis)            */
   int32_t prephase_s;     /* first block size of the monomial pre-phase
                              (default 8); >= 1                               */
+  sgm_orth orth;          /* second BCGS pass of blocks with s >= 2 (the
+                             column-wise s = 1 steps always use Alg. 4's);
+                             default SGM_ORTH_BCGS2                          */
 } sgm_opts;
 
 /* Fills *o (host) with the defaults: s_max 8, restart 64, max_restarts 100,
  * tol 1e-10, no preconditioner, scaled Newton, FP64, omega/omega_est rule,
  * estimator on, inner_tol 1e-6, max_outer 200, ritz_reuse 1, column-wise
- * pre-phase, prephase_s 8. */
+ * pre-phase, prephase_s 8, orth SGM_ORTH_BCGS2. */
 void sgm_opts_default(sgm_opts* o);
 
 typedef struct {
@@ -190,7 +203,7 @@ sgm_status sgm_grad_vals(sgm_matrix A, const double* lambda, const double* x,
  * of 64 elements, >= n, rows n..ldq-1 zero), float64 (SGM_FP64) or float32
  * (SGM_FP32_IR). */
 
-/* Matrix powers kernel (Alg. 4 line 3, Eq. (newtonrecurrence)): for
+/* Matrix powers kernel of Alg. 4 (Eq. (newtonrecurrence)): for
  * j = 0..s-1,  Q[:, c+j+1] = ((A - theta_j) Q[:, c+j] - delta_j Q[:, c+j-1])
  * / gamma_j, where records (device, double[3*n_rec]) hold (theta, gamma,
  * delta) per step and are used cyclically (j mod n_rec); delta_0 is
@@ -201,7 +214,9 @@ sgm_status sgm_mpk(sgm_matrix A, int transpose, sgm_precision precision,
 
 /* Block orthogonalisation of the s columns Q[:, i .. i+s-1] against the
  * orthonormal Q[:, 0 .. i-1]: BCGS2 with two partial CholQR passes
- * (Alg. 4 lines 5-17, Alg. 3 with the condition bound omega).  On return
+ * (Alg. 4's block orthogonalisation, Alg. 3 with the condition bound
+ * omega); orth selects how the second pass forms its Gram matrix (s >= 2;
+ * see sgm_orth).  On return
  * (host outputs): *p = accepted size (0 = breakdown), Q[:, i .. i+p-1] hold
  * the new orthonormal vectors, R_top (host, i x s, column-major, ld i) and
  * R_kk (host, s x s, ld s) hold R(1:i, k) and R(k, k) in their leading p
@@ -210,8 +225,9 @@ sgm_status sgm_mpk(sgm_matrix A, int transpose, sgm_precision precision,
 size_t sgm_block_ws_size(int64_t n_rows, int32_t i, int32_t s);
 sgm_status sgm_block_orth(sgm_precision precision, int64_t n_rows, void* Q,
                           int64_t ldq, int32_t i, int32_t s, double omega,
-                          void* ws, size_t ws_bytes, void* stream,
-                          int32_t* p, double* R_top, double* R_kk);
+                          sgm_orth orth, void* ws, size_t ws_bytes,
+                          void* stream, int32_t* p, double* R_top,
+                          double* R_kk);
 
 /* Shifts from a Hessenberg matrix (Sec. 3.4-3.5) computed on the GPU:
  * H (device, leading m0 x m0 block of an upper Hessenberg matrix,

@@ -345,7 +345,7 @@ def partial_cholesky(G, omega, cond="ice"):
 
 
 # ---------------------------------------------------------------------------
-# Block orthogonalisation: BCGS2 + partial CholQR (Alg. 4, lines 3-17)
+# Block orthogonalisation: BCGS2 + partial CholQR (Alg. 4)
 # ---------------------------------------------------------------------------
 
 @dataclass
@@ -368,12 +368,22 @@ def _right_divide(V, Z):
                                 check_finite=False).T
 
 
-def block_orth(Q, i, V, omega, work_dtype=np.float64, cond="ice"):
+def block_orth(Q, i, V, omega, work_dtype=np.float64, cond="ice",
+               pythagorean=False):
     """BCGS2 with partial CholQR on V (n x s) against Q[:, :i] (Alg. 4).
 
     Inter-orthogonalisation is block classical Gram-Schmidt applied twice;
     each intra step is a partial Cholesky QR (Alg. 3); the two R factors are
     combined as in Alg. 2/4 ("Combine both steps").
+
+    pythagorean=True is the low-synchronisation variant of the second pass
+    (not in the paper; its stability is checked by the orthogonality and
+    GMRES-minimiser pins, not proved here).  With U = Qk - Q_i R2 and
+    Q_i^T Q_i = I, U^T U = Qk^T Qk - R2^T R2 (Pythagoras), so the second
+    Gram is taken from Qk^T Qk, which the projection pass can form from
+    the same data, instead of from U after the update; the update and the
+    second triangular solve then become one step.  The first pass is the
+    paper's.
     """
     wd = work_dtype
     Qi = Q[:, :i]
@@ -387,8 +397,13 @@ def block_orth(Q, i, V, omega, work_dtype=np.float64, cond="ice"):
                        np.zeros((1, 1)), 0, kap1)
     Qk = _right_divide(V[:, :p1], Z.astype(wd)).astype(wd)
     R2 = Qi.T @ Qk                                   # second BCGS
-    Qk = Qk - Qi @ R2
-    G2 = (Qk.T @ Qk).astype(np.float64)
+    if pythagorean:
+        R2d = R2.astype(np.float64)
+        G2 = (Qk.T @ Qk).astype(np.float64) - R2d.T @ R2d
+        Qk = Qk - Qi @ R2
+    else:
+        Qk = Qk - Qi @ R2
+        G2 = (Qk.T @ Qk).astype(np.float64)
     p, Zt, _ = partial_cholesky(G2, omega, cond)     # second partial CholQR
     if p == 0:
         # breakdown after the first pass: the first column's coefficients
@@ -495,6 +510,7 @@ class Options:
     prephase: str = "cgs2"            # "cgs2": s = 1 steps; "monomial": s-step blocks
     prephase_s: int = 8               # first block size of the monomial pre-phase
     cond: str = "ice"                 # "ice" | "svd"
+    orth: str = "bcgs2"               # "bcgs2" | "bcgs2_pyth" (second Gram by Pythagoras)
     work_dtype: object = np.float64   # float32 => single-precision inner model
     record: bool = False              # keep per-block traces for tests
 
@@ -540,7 +556,7 @@ class _Engine:
                           else default_omega(self.u))
 
     def mpk(self, q, shifts: Shifts, s_eff):
-        """Matrix powers kernel (Alg. 4 line 3) with the recurrence of
+        """Matrix powers kernel of Alg. 4 with the recurrence of
         Eq. (newtonrecurrence): V_1 = Q_i, V_{j+1} = ((A - theta_j) V_j -
         delta_j V_{j-1}) / gamma_j.  Returns V_2 .. V_{s_eff+1} (n x s_eff).
         The shift records restart at the first one in every block.
@@ -617,7 +633,8 @@ class _Engine:
             else:
                 s_eff = min(s, m + 1 - nb)
             V = self.mpk(Q[:, nb - 1], sh, s_eff)
-            bq = block_orth(Q, nb, V, self.omega, self.wd, o.cond)
+            bq = block_orth(Q, nb, V, self.omega, self.wd, o.cond,
+                            pythagorean=(o.orth == "bcgs2_pyth" and s_eff > 1))
             if trace is not None and not in_pre and "first_block" not in trace:
                 trace["first_block"] = dict(kappas=list(bq.kappas1), p1=bq.p1,
                                             p=bq.p, s_eff=s_eff)
@@ -684,6 +701,8 @@ def solve(A, b, x0=None, opts: Options | None = None) -> Result:
     Right Jacobi preconditioning is column scaling (opts.precond="jacobi").
     """
     o = opts or Options()
+    if o.orth not in ("bcgs2", "bcgs2_pyth"):
+        raise ValueError(f"unknown orth {o.orth!r}")
     A = A.tocsr().astype(np.float64)
     n = A.shape[0]
     b = np.asarray(b, dtype=np.float64)

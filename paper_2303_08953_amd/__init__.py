@@ -26,6 +26,7 @@ BASIS = {"scaled_newton": 0, "newton": 1, "monomial": 2}
 PRECOND = {"none": 0, "jacobi": 1}
 PRECISION = {"fp64": 0, "fp32_ir": 1}
 PREPHASE = {"cgs2": 0, "monomial": 1}
+ORTH = {"bcgs2": 0, "bcgs2_pyth": 1}
 
 
 class SgmError(RuntimeError):
@@ -45,6 +46,7 @@ class Opts(C.Structure):
         ("ritz_reuse", C.c_int32),
         ("shifts_host", C.POINTER(C.c_double)), ("n_shifts", C.c_int32),
         ("prephase", C.c_int), ("prephase_s", C.c_int32),
+        ("orth", C.c_int),
     ]
 
 
@@ -91,8 +93,8 @@ _SIGS = [
     ("sgm_block_ws_size", C.c_size_t, [C.c_int64, C.c_int32, C.c_int32]),
     ("sgm_block_orth", C.c_int,
      [C.c_int, C.c_int64, _P, C.c_int64, C.c_int32, C.c_int32, C.c_double,
-      _P, C.c_size_t, _P, C.POINTER(C.c_int32), C.POINTER(C.c_double),
-      C.POINTER(C.c_double)]),
+      C.c_int, _P, C.c_size_t, _P, C.POINTER(C.c_int32),
+      C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     ("sgm_shifts_ws_size", C.c_size_t, [C.c_int32]),
     ("sgm_shifts", C.c_int,
      [_P, C.c_int32, C.c_int32, C.c_int, C.c_double, C.c_double, _P,
@@ -216,7 +218,7 @@ def make_opts(s_max=8, restart=64, max_restarts=100, tol=1e-10,
               precond="none", basis="scaled_newton", precision="fp64",
               omega=0.0, omega_est=0.0, use_estimator=True, transpose=False,
               inner_tol=1e-6, max_outer=200, ritz_reuse=True, shifts=None,
-              prephase="cgs2", prephase_s=8):
+              prephase="cgs2", prephase_s=8, orth="bcgs2"):
     o = Opts()
     lib().sgm_opts_default(C.byref(o))
     o.s_max, o.restart, o.max_restarts, o.tol = s_max, restart, max_restarts, tol
@@ -230,6 +232,7 @@ def make_opts(s_max=8, restart=64, max_restarts=100, tol=1e-10,
     o.ritz_reuse = int(bool(ritz_reuse))
     o.prephase = PREPHASE[prephase]
     o.prephase_s = int(prephase_s)
+    o.orth = ORTH[orth]
     keep = None
     if shifts is not None:
         z = np.asarray(shifts, dtype=np.complex128).ravel()
@@ -316,7 +319,7 @@ def mpk(A: Matrix, Q, ldq, c, s, records, transpose=False, precision="fp64",
 
 
 def block_orth(Q, n_rows, ldq, i, s, omega=0.0, precision="fp64",
-               stream=None):
+               stream=None, orth="bcgs2"):
     """sgm_block_orth on a flat column-major device tensor Q (in place).
     Returns (p, R_top (i x s), R_kk (s x s)) as numpy arrays."""
     torch = _torch()
@@ -327,7 +330,8 @@ def block_orth(Q, n_rows, ldq, i, s, omega=0.0, precision="fp64",
     Rt = np.zeros(i * s, dtype=np.float64)
     Rk = np.zeros(s * s, dtype=np.float64)
     _check(L.sgm_block_orth(PRECISION[precision], int(n_rows), _ptr(Q),
-                            int(ldq), int(i), int(s), float(omega), _ptr(ws),
+                            int(ldq), int(i), int(s), float(omega),
+                            ORTH[orth], _ptr(ws),
                             C.c_size_t(nbytes), _stream(stream), C.byref(p),
                             Rt.ctypes.data_as(C.POINTER(C.c_double)),
                             Rk.ctypes.data_as(C.POINTER(C.c_double))))

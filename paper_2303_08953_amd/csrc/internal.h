@@ -221,12 +221,28 @@ void gemv_update(QView<const T> Q, const double* y, int k,
 
 // Fused Q(:, b0:b0+p) = V Zinv (in place, p = min(nc, *pcount)) and
 // R2 (ka x nc, ld ldr) = Q(:, 0:ka)^T Q(:, b0:b0+p) (columns >= p zero).
+// With gram, R2 is (ka + nc) x nc (ldr >= ka + nc): rows ka.. hold the Gram
+// of the new block on and above the diagonal 16 x 16 tiles (zero below).
 // Returns false (and does nothing) for shapes it does not cover (float32,
 // ka > 64, nc > 32 or nc < 2); the caller then runs trsm_inv + gemm_tn.
 template <typename T>
 bool trsm_proj(QView<T> Q, int ka, int b0, int nc, const double* Zinv,
                int ldz, const int* pcount, int64_t nrows, double* R2, int ldr,
-               Partials& P, hipStream_t st);
+               Partials& P, hipStream_t st, bool gram = false);
+
+// Second pass of the Pythagorean BCGS2 variant in one pass over the block:
+// Q(:, b0:b0+p) = (Q(:, b0:b0+p) - Q(:, 0:ka) M(0:ka, 0:p)) Zinv(0:p, 0:p),
+// p = min(nc, *pcount), M ld ldm, Zinv upper triangular ld ldz.
+template <typename T>
+void update_trsm(QView<T> Q, int ka, int b0, int nc, const double* M,
+                 int ldm, const double* Zinv, int ldz, const int* pcount,
+                 int64_t nrows, hipStream_t st);
+
+// G2 (nc x nc, ld ldg) = Gk - R2^T R2 on the leading p1 = min(nc, *pcount)
+// block, zero elsewhere, from C = [R2; Gk] ((ka + nc) x nc, ld ldc, Gk read
+// on and above the diagonal).  Float64.
+void pyth_gram(const double* C, int ldc, int ka, int nc, const int* pcount,
+               double* G2, int ldg, hipStream_t st);
 
 // One-column blocks (s = 1), nrows a multiple of the 64-row panel:
 // C(0:ma) = Q(:, 0:ma)^T v with v = Q(:, vcol); pmask (device, may be

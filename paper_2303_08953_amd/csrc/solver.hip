@@ -156,12 +156,13 @@ double ms_since(Clock::time_point t) {
 
 // ------------------------------------------------------------------ block
 // Block orthogonalisation of V = Q(:, nb : nb+s-1) against Q(:, 0 : nb-1):
-// BCGS2 with two partial CholQR passes (Alg. 4 lines 5-17).  The accepted
+// BCGS2 with two partial CholQR passes (Alg. 4).  The accepted
 // sizes stay on the device (ctrl[C_P1], ctrl[C_P2]); later kernels read
 // them, so the sequence needs no host synchronisation.
 template <typename T>
 void orth_block(QView<T> Q, int64_t nrows, int nb, int s, double omega,
-                Work& w, hipStream_t st, bool combine = true) {
+                Work& w, hipStream_t st, bool combine = true,
+                bool pyth = false) {
   const QView<const T> Qc = Q.template as<const T>();
   int* p1 = w.ctrl + C_P1;
   int* p2 = w.ctrl + C_P2;
@@ -189,6 +190,26 @@ void orth_block(QView<T> Q, int64_t nrows, int nb, int s, double omega,
   // first partial CholQR: p1, Z; V(:, 0:p1) = V Z^{-1}
   pchol_ice(w.G, w.lds, s, nullptr, omega, w.Z, w.Zinv, w.lds, p1,
             w.pchol_scr, st);
+  if (pyth) {
+    // Pythagorean second pass: Q_1 = V Zinv, and [R2; Gk] = [Q Q_1]^T Q_1
+    // in one (nb + s) x s output (the Gram of Q_1 from the same pass);
+    // G2 = Gk - R2^T R2; then (Q_1 - Q R2) Zt^{-1} in one pass.
+    if (w.ldw < nb + s)
+      throw Error{SGM_EINVAL, "orth_block: R2 workspace too short"};
+    if (!trsm_proj<T>(Q, nb, nb, s, w.Zinv, w.lds, p1, nrows, w.R2, w.ldw,
+                      w.P, st, true)) {
+      trsm_inv<T>(Q, nb, s, w.Zinv, w.lds, p1, nrows, st);
+      gemm_tn<T>(Qc, 0, nb + s, nb, s, p1, nrows, w.R2, w.ldw, w.P, st);
+    }
+    pyth_gram(w.R2, w.ldw, nb, s, p1, w.G2, w.lds, st);
+    pchol_ice(w.G2, w.lds, s, p1, omega, w.Zt, w.Ztinv, w.lds, p2,
+              w.pchol_scr, st);
+    update_trsm<T>(Q, nb, nb, s, w.R2, w.ldw, w.Ztinv, w.lds, p2, nrows, st);
+    if (combine)
+      combine_r(w.W, w.ldw, w.R2, w.ldw, w.Z, w.Zt, w.lds, nb, w.ctrl, w.Rtop,
+                w.ldw, w.Rkk, w.lds, st);
+    return;
+  }
   // V(:, 0:p1) = V Zinv, then the second BCGS projection R2 = Q^T V on
   // the p1 accepted columns (fused when the shape allows)
   if (!trsm_proj<T>(Q, nb, nb, s, w.Zinv, w.lds, p1, nrows, w.R2, w.ldw, w.P,
@@ -348,7 +369,8 @@ struct Engine {
       spmv_mpk<T>(S, vals, Q(), nb - 1 + j, jprev, nb + j, rec, q, st);
     }
     SGM_HIP(hipEventRecord(ev[1], st));
-    orth_block<T>(Q(), ld, nb, s_eff, omega, w, st, false);
+    orth_block<T>(Q(), ld, nb, s_eff, omega, w, st, false,
+                  o.orth == SGM_ORTH_BCGS2_PYTH);
     SGM_HIP(hipEventRecord(ev[2], st));
     block_tail(w.W, w.R2, w.ldw, w.Z, w.Zt, w.Zinv, w.Ztinv, w.lds, nb,
                w.ctrl, nullptr, nullptr, w.Hraw, w.Hr, w.ldh, w.cs, w.sn, w.g,
@@ -640,6 +662,8 @@ void validate_opts(const sgm_opts* o) {
                   o->prephase == SGM_PREPHASE_MONOMIAL,
               "unknown prephase");
   SGM_REQUIRE(o->prephase_s >= 1, "prephase_s must be >= 1");
+  SGM_REQUIRE(o->orth == SGM_ORTH_BCGS2 || o->orth == SGM_ORTH_BCGS2_PYTH,
+              "unknown orth");
 }
 
 int nshift_max(const sgm_opts& o) {
@@ -660,7 +684,7 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Workspace of the stand-alone block orthogonalisation.
 void block_layout(Arena& a, Work& w, int i, int s) {
-  w.ldw = std::max(i, 1);
+  w.ldw = std::max(i, 1) + s;  // room for [R2; Gram] of the Pythagorean pass
   w.lds = s;
   w.P.cap = std::max<int64_t>((int64_t)1 << 22, (int64_t)16 * (i + 1) * s);
   w.P.buf = a.take<double>(w.P.cap);
@@ -793,6 +817,7 @@ void sgm_opts_default(sgm_opts* o) {
   o->n_shifts = 0;
   o->prephase = SGM_PREPHASE_CGS2;
   o->prephase_s = 8;
+  o->orth = SGM_ORTH_BCGS2;
 }
 
 sgm_status sgm_workspace_size(sgm_matrix A, const sgm_opts* o,
@@ -920,8 +945,9 @@ size_t sgm_block_ws_size(int64_t n_rows, int32_t i, int32_t s) {
 
 sgm_status sgm_block_orth(sgm_precision precision, int64_t n_rows, void* Q,
                           int64_t ldq, int32_t i, int32_t s, double omega,
-                          void* ws, size_t ws_bytes, void* stream, int32_t* p,
-                          double* R_top, double* R_kk) {
+                          sgm_orth orth, void* ws, size_t ws_bytes,
+                          void* stream, int32_t* p, double* R_top,
+                          double* R_kk) {
   SGM_API_BEGIN
   SGM_REQUIRE(Q != nullptr && p != nullptr, "NULL argument");
   SGM_REQUIRE(n_rows >= 1 && ldq >= n_rows && ldq % kLdAlign == 0,
@@ -930,6 +956,8 @@ sgm_status sgm_block_orth(sgm_precision precision, int64_t n_rows, void* Q,
   SGM_REQUIRE(precision == SGM_FP64 || precision == SGM_FP32_IR,
               "unknown precision");
   SGM_REQUIRE(omega >= 0.0, "omega must be >= 0");
+  SGM_REQUIRE(orth == SGM_ORTH_BCGS2 || orth == SGM_ORTH_BCGS2_PYTH,
+              "unknown orth");
   const size_t need = sgm_block_ws_size(n_rows, i, s);
   SGM_REQUIRE(ws != nullptr && ws_bytes >= need, "workspace too small");
   Arena a;
@@ -940,18 +968,21 @@ sgm_status sgm_block_orth(sgm_precision precision, int64_t n_rows, void* Q,
   hipStream_t st = as_stream(stream);
   const bool f32 = precision == SGM_FP32_IR;
   const double om = omega > 0 ? omega : default_omega(f32);
+  const bool pyth = orth == SGM_ORTH_BCGS2_PYTH;
   if (f32)
     orth_block<float>(colmajor_view<float>(static_cast<float*>(Q), ldq), ldq,
-                      i, s, om, w, st);
+                      i, s, om, w, st, true, pyth);
   else
     orth_block<double>(colmajor_view<double>(static_cast<double*>(Q), ldq),
-                       ldq, i, s, om, w, st);
+                       ldq, i, s, om, w, st, true, pyth);
   int ctrl[C_NCTRL];
   SGM_HIP(hipMemcpyAsync(ctrl, w.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost,
                          st));
   if (R_top)
-    SGM_HIP(hipMemcpyAsync(R_top, w.Rtop, sizeof(double) * (size_t)i * s,
-                           hipMemcpyDeviceToHost, st));
+    SGM_HIP(hipMemcpy2DAsync(R_top, sizeof(double) * (size_t)i, w.Rtop,
+                             sizeof(double) * (size_t)w.ldw,
+                             sizeof(double) * (size_t)i, (size_t)s,
+                             hipMemcpyDeviceToHost, st));
   if (R_kk)
     SGM_HIP(hipMemcpyAsync(R_kk, w.Rkk, sizeof(double) * (size_t)s * s,
                            hipMemcpyDeviceToHost, st));

@@ -18,6 +18,8 @@
 // floating-point atomics, so results are bitwise reproducible.
 #include "internal.h"
 
+#include <type_traits>
+
 namespace sgm {
 
 namespace {
@@ -522,7 +524,13 @@ __global__ __launch_bounds__(kBlock) void k_update(
 // (q, t) needs in lane group g; the matching A operand, column
 // 16 i + c16 of Q at those MT rows, is one MT-vector load.
 // Requires ka <= 16 * MQ (MQ column tiles of Q accumulate in registers).
-template <typename T, int NT, int MT, int MQ>
+// With GK the Gram Q_k^T Q_k is accumulated as well, from the same
+// registers (in the result layout, register q of tile j is the MFMA operand
+// for column 16 j + c16 over the rows of step (q, t), for both sides of a
+// T^T T product), and the partial holds the (ka + nc) x nc matrix
+// [Q(:, 0:ka) Q_k]^T Q_k: rows ka.. are the Gram, written for the tiles on
+// and above the diagonal (zeros below).
+template <typename T, int NT, int MT, int MQ, bool GK>
 __global__ __launch_bounds__(kBlock) void k_trsm_proj(
     QView<T> Q, int ka, int b0c, int nc, const double* __restrict__ Zinv,
     int ldz, const int* __restrict__ pcount, int64_t nrows,
@@ -559,6 +567,10 @@ __global__ __launch_bounds__(kBlock) void k_trsm_proj(
   for (int i = 0; i < MQ; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) r2[i][j] = vzero<V>();
+  constexpr int NG = GK ? NT * (NT + 1) / 2 : 0;
+  V gk[NG > 0 ? NG : 1];
+#pragma unroll
+  for (int t = 0; t < (NG > 0 ? NG : 1); ++t) gk[t] = vzero<V>();
 
   for (int64_t rb = blockIdx.x; rb < nblocks; rb += gridDim.x) {
     const int64_t r0 = rb * rows_per_block + wave * rows_per_wave;
@@ -615,30 +627,44 @@ __global__ __launch_bounds__(kBlock) void k_trsm_proj(
           for (int j = 0; j < NT; ++j)
             r2[i][j] = mfma(qa[q][t], acc[t][j][q], r2[i][j]);
     }
+    if constexpr (GK) {
+      int tix = 0;
+#pragma unroll
+      for (int j1 = 0; j1 < NT; ++j1)
+#pragma unroll
+        for (int j2 = j1; j2 < NT; ++j2) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+              gk[tix] = mfma(acc[t][j1][q], acc[t][j2][q], gk[tix]);
+          ++tix;
+        }
+    }
   }
   // fixed-order sum of the four wavefronts through LDS, then one partial
   // per workgroup
   __syncthreads();
   double* red = reinterpret_cast<double*>(smem_raw);
-  constexpr int NE = MQ * NT * 4;
+  constexpr int NR = MQ * NT;  // projection tiles, then the Gram tiles
   for (int w = kBlock / kWave - 1; w >= 1; --w) {
     if (wave == w) {
 #pragma unroll
-      for (int i = 0; i < MQ; ++i)
+      for (int x = 0; x < NR + NG; ++x)
 #pragma unroll
-        for (int j = 0; j < NT; ++j)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int e = ((i * NT + j) * 4 + q) * kWave + lane;
-            double v = (double)r2[i][j][q];
-            if (w < kBlock / kWave - 1) v += red[e];
-            red[e] = v;
-          }
+        for (int q = 0; q < 4; ++q) {
+          const int e = (x * 4 + q) * kWave + lane;
+          double v = (double)(x < NR ? r2[x / NT][x % NT][q]
+                                     : gk[(x - NR) % (NG > 0 ? NG : 1)][q]);
+          if (w < kBlock / kWave - 1) v += red[e];
+          red[e] = v;
+        }
     }
     __syncthreads();
   }
   if (wave == 0) {
-    double* out = part + (int64_t)blockIdx.x * ka * nc;
+    const int ldo = GK ? ka + nc : ka;
+    double* out = part + (int64_t)blockIdx.x * ldo * nc;
 #pragma unroll
     for (int i = 0; i < MQ; ++i)
 #pragma unroll
@@ -649,10 +675,234 @@ __global__ __launch_bounds__(kBlock) void k_trsm_proj(
           const int row = i * 16 + drow<T>(g, q);
           const int col = j * 16 + c16;
           if (row < ka && col < nc)
-            out[(int64_t)col * ka + row] = (double)r2[i][j][q] + red[e];
+            out[(int64_t)col * ldo + row] = (double)r2[i][j][q] + red[e];
         }
+    if constexpr (GK) {
+      int tix = 0;
+#pragma unroll
+      for (int j1 = 0; j1 < NT; ++j1)
+#pragma unroll
+        for (int j2 = 0; j2 < NT; ++j2) {
+          const bool upper = j2 >= j1;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int row = j1 * 16 + drow<T>(g, q);
+            const int col = j2 * 16 + c16;
+            if (row < nc && col < nc) {
+              double v = 0.0;
+              if (upper) {
+                const int e = ((NR + tix) * 4 + q) * kWave + lane;
+                v = (double)gk[tix][q] + red[e];
+              }
+              out[(int64_t)col * ldo + ka + row] = v;
+            }
+          }
+          if (upper) ++tix;
+        }
+    }
   }
-  (void)NE;
+}
+
+// Second pass of the Pythagorean BCGS2 variant, update and triangular
+// solve in one pass over the block:
+//   V(:, 0:p) = (V(:, 0:p) - Q(:, 0:ka) M(0:ka, 0:p)) Zinv(0:p, 0:p),
+// V = Q(:, b0c : b0c+nc), p = min(nc, *pcount) (the second pass's accepted
+// size; columns p.. are left as they are), Zinv upper triangular.
+// The update is computed transposed, U^T = V^T - M^T Q^T: the same MFMA as
+// the plain update with the operands swapped (the staged M supplies the A
+// side, Q the B side, with unchanged loads), so tile acc[t][j] holds U^T
+// with lane (g, c16) owning row r0 + MT * c16 + t and, in result register
+// q, column 16 j + drow(g, q).  That register is the B operand of the next
+// product Y^T = Zinv^T U^T for MFMA step (j, q), whose k slot g is then
+// column 16 j + drow(g, q): no transpose through LDS is needed.  The
+// result Y^T has the same layout, so each lane stores MT consecutive rows
+// of a column.  Output tiles are formed from the last to the first: tile
+// jo needs U tiles 0..jo only, so it can overwrite U tile jo.
+// LDS: Zinv (W16 x W16) then the staged -M (kc x W16).
+template <typename T, int NT, int MT>
+__global__ __launch_bounds__(kBlock) void k_update_trsm(
+    QView<T> Q, int ka, int b0c, int nc, const double* __restrict__ M,
+    int ldm, const double* __restrict__ Zinv, int ldz,
+    const int* __restrict__ pcount, int64_t nrows, int kc) {
+  typedef typename Vec4<T>::type V;
+  extern __shared__ char smem_raw[];
+  constexpr int W16 = NT * 16;
+  T* Zs = reinterpret_cast<T*>(smem_raw);
+  T* Ms = Zs + W16 * W16;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int g = lane / 16, c16 = lane % 16;
+  const int p = min(nc, *pcount);
+  if (p <= 0) return;  // uniform over the grid
+  const int ka4 = (ka + 3) & ~3;
+  const bool single = ka4 <= kc;
+  const int64_t cs = Q.cstride;
+  const int64_t rows_per_wave = 16 * MT;
+  const int64_t rows_per_block = rows_per_wave * (kBlock / kWave);
+  const int64_t nblocks = (nrows + rows_per_block - 1) / rows_per_block;
+
+  for (int e = threadIdx.x; e < W16 * W16; e += kBlock) {
+    const int k = e / W16, c = e % W16;
+    Zs[e] = (T)(k <= c && c < p ? Zinv[(int64_t)c * ldz + k] : 0.0);
+  }
+  auto stage = [&](int k0) {
+    for (int e = threadIdx.x; e < kc * W16; e += kBlock) {
+      const int kk = e / W16, cc = e % W16;
+      const int k = k0 + kk;
+      Ms[e] = (T)(k < ka && cc < p ? -M[(int64_t)cc * ldm + k] : 0.0);
+    }
+  };
+  if (single) stage(0);
+  __syncthreads();
+
+  for (int64_t rb = blockIdx.x; rb < nblocks; rb += gridDim.x) {
+    const int64_t r0 = rb * rows_per_block + wave * rows_per_wave;
+    const bool active = r0 < nrows;
+    T* const rbase = Q.base + Q.row_off(r0);
+    T* const B = rbase + (int64_t)b0c * cs;
+    V acc[MT][NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = j * 16 + drow<T>(g, q);
+        T v[MT];
+        if (active && c < p) {
+          load_rows<T, MT>(B + (int64_t)c * cs + MT * c16, v);
+        } else {
+#pragma unroll
+          for (int t = 0; t < MT; ++t) v[t] = (T)0;
+        }
+#pragma unroll
+        for (int t = 0; t < MT; ++t) acc[t][j][q] = v[t];
+      }
+    for (int k0 = 0; k0 < ka4; k0 += kc) {
+      if (!single) {
+        __syncthreads();
+        stage(k0);
+        __syncthreads();
+      }
+      const int kend = min(kc, ka4 - k0);
+      if (active) {
+        const T* base = rbase + MT * c16;
+        auto kstep = [&](int kk, const T (&a)[MT]) {
+          const T* mrow = Ms + (kk + g) * W16 + c16;
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            const T av = mrow[j * 16];
+#pragma unroll
+            for (int t = 0; t < MT; ++t) acc[t][j] = mfma(av, a[t], acc[t][j]);
+          }
+        };
+        // a column past the end reads column 0, whose staged M row is zero
+        auto kload = [&](int kk, T (&a)[MT]) {
+          const int k = k0 + kk + g;
+          load_rows<T, MT>(base + (int64_t)(k < ka ? k : 0) * cs, a);
+        };
+        int kk = 0;
+        const int kend16 = kend & ~15;
+        if (kend16 > 0) {
+          T a0[MT], a1[MT], a2[MT], a3[MT];
+          kload(0, a0);
+          kload(4, a1);
+          kload(8, a2);
+          kload(12, a3);
+          for (; kk < kend16; kk += 16) {
+            T n0[MT], n1[MT], n2[MT], n3[MT];
+            const bool more = kk + 16 < kend16;
+            if (more) {
+              kload(kk + 16, n0);
+              kload(kk + 20, n1);
+              kload(kk + 24, n2);
+              kload(kk + 28, n3);
+            }
+            kstep(kk, a0);
+            kstep(kk + 4, a1);
+            kstep(kk + 8, a2);
+            kstep(kk + 12, a3);
+            if (more) {
+#pragma unroll
+              for (int t = 0; t < MT; ++t) {
+                a0[t] = n0[t];
+                a1[t] = n1[t];
+                a2[t] = n2[t];
+                a3[t] = n3[t];
+              }
+            }
+          }
+        }
+        for (; kk < kend; kk += 4) {
+          T a0[MT];
+          kload(kk, a0);
+          kstep(kk, a0);
+        }
+      }
+    }
+    if (active) {
+      // Y^T = Zinv^T U^T, output tiles from the last to the first
+#pragma unroll
+      for (int jo = NT - 1; jo >= 0; --jo) {
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+          V o = vzero<V>();
+#pragma unroll
+          for (int jt = 0; jt <= jo; ++jt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const T zv = Zs[(jt * 16 + drow<T>(g, q)) * W16 + jo * 16 + c16];
+              o = mfma(zv, acc[t][jt][q], o);
+            }
+          acc[t][jo] = o;
+        }
+      }
+#pragma unroll
+      for (int jo = 0; jo < NT; ++jo)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = jo * 16 + drow<T>(g, q);
+          if (c < p) {
+            T v[MT];
+#pragma unroll
+            for (int t = 0; t < MT; ++t) v[t] = acc[t][jo][q];
+            store_rows<T, MT>(B + (int64_t)c * cs + MT * c16, v);
+          }
+        }
+    }
+  }
+}
+
+// Second Gram of the Pythagorean BCGS2 variant (float64):
+//   G2(a, b) = Gk(a, b) - sum_k R2(k, a) R2(k, b),  a, b < p1 = *pcount,
+// zero outside, from C = [R2; Gk] ((ka + nc) x nc, ld ldc; Gk is read on
+// and above the diagonal).  One workgroup per column b: R2(:, b) is staged
+// in LDS; each wavefront takes columns a, its lanes split k (lane l sums
+// k = l, l + 64, ...), then a fixed xor tree.  The sums for (a, b) and
+// (b, a) multiply the same pairs in the same order, so G2 is exactly
+// symmetric.  Deterministic.
+__global__ __launch_bounds__(256) void k_pyth_gram(
+    const double* __restrict__ C, int ldc, int ka, int nc,
+    const int* __restrict__ pcount, double* __restrict__ G2, int ldg) {
+  extern __shared__ char smem_raw[];
+  double* rb = reinterpret_cast<double*>(smem_raw);
+  const int b = blockIdx.x;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int p1 = min(nc, *pcount);
+  const bool live_b = b < p1;
+  if (live_b)
+    for (int k = threadIdx.x; k < ka; k += blockDim.x)
+      rb[k] = C[(int64_t)b * ldc + k];
+  __syncthreads();
+  for (int a = wave; a < nc; a += blockDim.x / kWave) {
+    double v = 0.0;
+    if (live_b && a < p1) {
+      double s = 0.0;
+      const double* ca = C + (int64_t)a * ldc;
+      for (int k = lane; k < ka; k += kWave) s += ca[k] * rb[k];
+      for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+      const int lo = a < b ? a : b, hi = a < b ? b : a;
+      v = C[(int64_t)hi * ldc + ka + lo] - s;
+    }
+    if (lane == 0) G2[(int64_t)b * ldg + a] = v;
+  }
 }
 
 // x(r) += scale * sum_j Q(r, j) y(j), j < k (float64 accumulation).  A
@@ -991,25 +1241,27 @@ void gemv_update(QView<const T> Q, const double* y, int k,
 }
 
 namespace {
-template <typename T, int NT, int MQ>
+template <typename T, int NT, int MQ, bool GK>
 void launch_trsm_proj(QView<T> Q, int ka, int b0, int nc, const double* Zinv,
                       int ldz, const int* pcount, int64_t nrows, double* R2,
                       int ldr, Partials& P, hipStream_t st) {
   constexpr int MT = 4;
+  const int ldo = GK ? ka + nc : ka;
   const int64_t rows_per_block = 16 * MT * (kBlock / kWave);
   const int64_t nblocks = ceil_div(nrows, rows_per_block);
   int64_t grid = nblocks < kTargetGroups ? nblocks : kTargetGroups;
   if (grid < 1) grid = 1;
-  if (grid * ka * nc > P.cap) grid = P.cap / ((int64_t)ka * nc);
+  if (grid * ldo * nc > P.cap) grid = P.cap / ((int64_t)ldo * nc);
   if (grid < 1) throw Error{SGM_EINVAL, "partial scratch too small"};
   const size_t stage = (size_t)(((nc + 3) & ~3)) * NT * 16 * sizeof(T);
-  const size_t red = (size_t)MQ * NT * 4 * kWave * sizeof(double);
+  const int ng = GK ? NT * (NT + 1) / 2 : 0;
+  const size_t red = (size_t)(MQ * NT + ng) * 4 * kWave * sizeof(double);
   const size_t lds = stage > red ? stage : red;
-  hipLaunchKernelGGL((k_trsm_proj<T, NT, MT, MQ>), dim3((unsigned)grid),
+  hipLaunchKernelGGL((k_trsm_proj<T, NT, MT, MQ, GK>), dim3((unsigned)grid),
                      dim3(kBlock), lds, st, Q, ka, b0, nc, Zinv, ldz, pcount,
                      nrows, P.buf);
   SGM_CHECK_LAUNCH();
-  launch_reduce(P.buf, grid, ka, nc, R2, ldr, 0, st);
+  launch_reduce(P.buf, grid, ldo, nc, R2, ldr, 0, st);
 }
 }  // namespace
 
@@ -1021,19 +1273,79 @@ void launch_trsm_proj(QView<T> Q, int ka, int b0, int nc, const double* Zinv,
 template <typename T>
 bool trsm_proj(QView<T> Q, int ka, int b0, int nc, const double* Zinv,
                int ldz, const int* pcount, int64_t nrows, double* R2, int ldr,
-               Partials& P, hipStream_t st) {
+               Partials& P, hipStream_t st, bool gram) {
   if (sizeof(T) != 8 || ka < 1 || nc < 2 || ka > 64 || nc > 32) return false;
+  if (gram && ldr < ka + nc)
+    throw Error{SGM_EINVAL, "trsm_proj: output too short for the Gram rows"};
   const int nt = (nc + 15) / 16, mq = (ka + 15) / 16;
 #define SGM_TP(NTv, MQv)                                                      \
   if (nt == NTv && mq <= MQv) {                                               \
-    launch_trsm_proj<T, NTv, MQv>(Q, ka, b0, nc, Zinv, ldz, pcount, nrows,    \
-                                  R2, ldr, P, st);                            \
+    if (gram)                                                                 \
+      launch_trsm_proj<T, NTv, MQv, true>(Q, ka, b0, nc, Zinv, ldz, pcount,   \
+                                          nrows, R2, ldr, P, st);             \
+    else                                                                      \
+      launch_trsm_proj<T, NTv, MQv, false>(Q, ka, b0, nc, Zinv, ldz, pcount,  \
+                                           nrows, R2, ldr, P, st);            \
     return true;                                                              \
   }
   SGM_TP(1, 2) SGM_TP(1, 4)
   SGM_TP(2, 2) SGM_TP(2, 4)
 #undef SGM_TP
   return false;
+}
+
+// Fused when Zinv fits in LDS beside the staged M (up to 64 columns);
+// wider blocks take the plain update and the triangular solve as two
+// passes.
+template <typename T>
+void update_trsm(QView<T> Q, int ka, int b0, int nc, const double* M,
+                 int ldm, const double* Zinv, int ldz, const int* pcount,
+                 int64_t nrows, hipStream_t st) {
+  if (nc <= 0) return;
+  const int nt = (nc + 15) / 16;
+  if (nt > 4) {
+    Partials none;
+    update_gram<T>(Q, 0, ka, b0, nc, M, ldm, pcount, nrows, nullptr, 0, none,
+                   st);
+    trsm_inv<T>(Q, b0, nc, Zinv, ldz, pcount, nrows, st);
+    return;
+  }
+  auto launch = [&](auto nt_c, auto mt_c) {
+    constexpr int NTv = decltype(nt_c)::value, MTv = decltype(mt_c)::value;
+    constexpr int W16 = NTv * 16;
+    const int ka4 = (ka + 3) & ~3;
+    int kc = kLdsBudget / (W16 * (int)sizeof(T));
+    kc &= ~3;
+    if (kc > ka4) kc = ka4 < 4 ? 4 : ka4;
+    const size_t lds = (size_t)(W16 * W16 + kc * W16) * sizeof(T);
+    const int64_t rows_per_block = 16 * MTv * (kBlock / kWave);
+    const int64_t nblocks = ceil_div(nrows, rows_per_block);
+    int64_t grid = nblocks < kTargetGroups ? nblocks : kTargetGroups;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL((k_update_trsm<T, NTv, MTv>), dim3((unsigned)grid),
+                       dim3(kBlock), lds, st, Q, ka, b0, nc, M, ldm, Zinv,
+                       ldz, pcount, nrows, kc);
+    SGM_CHECK_LAUNCH();
+  };
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  using I4 = std::integral_constant<int, 4>;
+  if (nt == 1) launch(I1{}, I4{});
+  else if (nt == 2) launch(I2{}, I4{});
+  else if (nt == 3) launch(I3{}, I2{});
+  else launch(I4{}, I2{});
+}
+
+void pyth_gram(const double* C, int ldc, int ka, int nc, const int* pcount,
+               double* G2, int ldg, hipStream_t st) {
+  if (nc <= 0) return;
+  if ((size_t)ka * sizeof(double) > 64 * 1024)
+    throw Error{SGM_EINVAL, "pyth_gram: too many prior columns"};
+  const size_t lds = sizeof(double) * (size_t)(ka > 0 ? ka : 1);
+  hipLaunchKernelGGL(k_pyth_gram, dim3((unsigned)nc), dim3(256), lds, st, C,
+                     ldc, ka, nc, pcount, G2, ldg);
+  SGM_CHECK_LAUNCH();
 }
 
 namespace {
@@ -1109,7 +1421,10 @@ void col_scale(QView<T> Q, int vcol, const double* z, const int* pmask,
                              int64_t, hipStream_t);                          \
   template bool trsm_proj<T>(QView<T>, int, int, int, const double*, int,    \
                              const int*, int64_t, double*, int, Partials&,   \
-                             hipStream_t);
+                             hipStream_t, bool);                             \
+  template void update_trsm<T>(QView<T>, int, int, int, const double*, int,  \
+                               const double*, int, const int*, int64_t,      \
+                               hipStream_t);
 SGM_INST(double)
 SGM_INST(float)
 #undef SGM_INST

@@ -65,8 +65,8 @@ def test_opts_default_and_host_validation(L):
     assert b"row_ptr" in L.sgm_last_error() or b"nnz" in L.sgm_last_error()
     assert L.sgm_solve(None, None, None, None, C.byref(o), None, 0, None,
                        None, 0, None, 0, None) == sgm.EINVAL
-    assert L.sgm_block_orth(0, 10, None, 64, 1, 1, 0.0, None, 0, None, None,
-                            None, None) == sgm.EINVAL
+    assert L.sgm_block_orth(0, 10, None, 64, 1, 1, 0.0, 0, None, 0, None,
+                            None, None, None) == sgm.EINVAL
     assert L.sgm_status_string(sgm.ENUMERIC) == b"numerical breakdown (NaN/Inf)"
     assert L.sgm_block_ws_size(100, 0, 4) == 0
     assert L.sgm_block_ws_size(100, 4, 4) > 0

@@ -102,6 +102,14 @@ CASES = [
      "return BlockQR(0, V[:, :0], W[:, :1].astype(np.float64),",
      "return BlockQR(0, V[:, :0], 0.5 * W[:, :1].astype(np.float64),",
      [(P.test_happy_breakdown_eigenvector_rhs, ())]),
+    ("pythagorean_gram_sign",
+     "G2 = (Qk.T @ Qk).astype(np.float64) - R2d.T @ R2d",
+     "G2 = (Qk.T @ Qk).astype(np.float64) + R2d.T @ R2d",
+     [(P.test_pythagorean_second_pass_block, (1e-12,))]),
+    ("pythagorean_gram_drops_projection",
+     "G2 = (Qk.T @ Qk).astype(np.float64) - R2d.T @ R2d",
+     "G2 = (Qk.T @ Qk).astype(np.float64) - 0.0 * (R2d.T @ R2d)",
+     [(P.test_pythagorean_second_pass_block, (1e-12,))]),
     ("givens_rhs_not_rotated",
      "self.g[col + 1] = -ss * gc",
      "self.g[col + 1] = ss * gc",

@@ -576,3 +576,81 @@ def test_monomial_prephase_matches_columnwise_prephase():
     assert np.all(np.abs(ha - hb) <= 1e-8 * ha)
     assert ra.iters == rb.iters
     assert np.linalg.norm(ra.x - rb.x) <= 1e-10 * np.linalg.norm(ra.x)
+
+
+def _near_span_block(n, i, s, delta, seed):
+    """Q_i orthonormal (n x i) and V = Q_i C + delta N: with delta small the
+    block lies almost in span(Q_i), so one BCGS pass leaves components along
+    Q_i of order u/delta and the second pass has real work to do."""
+    rng = np.random.default_rng(seed)
+    Qi, _ = np.linalg.qr(rng.standard_normal((n, i)))
+    V = Qi @ rng.standard_normal((i, s)) + delta * rng.standard_normal((n, s))
+    return Qi, V
+
+
+@pytest.mark.parametrize("delta", [1.0, 1e-12])
+def test_pythagorean_second_pass_block(delta):
+    """f3 variant of the second BCGS pass against Householder QR of [Q_i V]
+    with V = Q_i C + delta N (full rank): both variants keep every column,
+    reconstruct V, keep [Q_i Q_k] orthonormal to rounding, and give the Q
+    factor's last s columns and the R columns (signs fixed by a positive R
+    diagonal) to the accuracy the problem allows, u kappa([Q_i V]) with
+    kappa ~ 1/delta.  At delta = 1e-12 the first pass leaves R2 ~ 1e-4, so
+    the R2^T R2 term of the Pythagorean Gram shifts G2 by ~1e-8: dropping
+    it or flipping its sign breaks the orthogonality bound."""
+    n, i, s = 3000, 20, 12
+    Qi, V = _near_span_block(n, i, s, delta, seed=11)
+    Qh, Rh = np.linalg.qr(np.concatenate([Qi, V], 1))
+    sg = np.sign(np.diag(Rh))
+    Qh, Rh = Qh * sg, (Rh.T * sg).T
+    tol = 1e-12 / delta          # u kappa, with margin
+    om = o.default_omega(o.U64)
+    for pyth in (False, True):
+        bq = o.block_orth(np.asfortranarray(Qi.copy()), i, V.copy(), om,
+                          pythagorean=pyth)
+        assert bq.p == s
+        assert o.loo(np.concatenate([Qi, bq.Qk], 1)) <= 1e-12
+        rec = Qi @ bq.R_top + bq.Qk @ bq.R_kk
+        assert np.linalg.norm(rec - V) <= 1e-15 * math.sqrt(n) * np.linalg.norm(V)
+        assert np.abs(bq.Qk - Qh[:, i:]).max() <= tol
+        # R_top is in Q_i's frame (Householder's first i columns may differ
+        # from Q_i by signs and rounding)
+        Rt = (Qi.T @ Qh[:, :i]) @ Rh[:i, i:]
+        assert np.abs(bq.R_top - Rt).max() <= 1e-10 * np.abs(Rt).max()
+        Rk = Rh[i:, i:]
+        assert np.abs(bq.R_kk - Rk).max() <= tol * np.abs(Rk).max()
+
+
+def test_pythagorean_solves_keep_the_pins():
+    """The f3 variant through whole solves: s-step iterates equal the GMRES
+    minimisers, the basis stays orthonormal, the Arnoldi relation holds,
+    and a full solve reaches the classical variant's solution."""
+    n = 60
+    A = small_nonsym(n, 3, shift=4.0)
+    Ad = A.toarray()
+    b = np.random.default_rng(4).standard_normal(n)
+    x0 = np.random.default_rng(5).standard_normal(n) * 0.1
+    for basis in ("monomial", "newton", "scaled_newton"):
+        for s in (3, 5):
+            r = o.solve(A, b, x0, o.Options(s_max=s, restart=17, max_restarts=0,
+                                            tol=1e-300, basis=basis,
+                                            use_estimator=False,
+                                            orth="bcgs2_pyth"))
+            xk = o.gmres_iterates_dense(Ad, b, x0, 17)
+            assert np.linalg.norm(r.x - xk) <= 1e-8 * np.linalg.norm(xk)
+        _, _, r = _conv_diff_run(basis=basis, max_restarts=0, tol=1e-300,
+                                 orth="bcgs2_pyth")
+        Q = r.trace["Q_first_cycle"]
+        assert o.loo(Q) <= 1e-12
+    A, b, r = _conv_diff_run(max_restarts=0, tol=1e-300, orth="bcgs2_pyth")
+    H = r.trace["H_first_cycle"]
+    Q = r.trace["Q_first_cycle"]
+    k = H.shape[1]
+    M = csr(A)
+    assert (np.linalg.norm(M @ Q[:, :k] - Q @ H)
+            / (sp.linalg.norm(M) * math.sqrt(k))) <= 1e-12
+    _, _, ra = _conv_diff_run(max_restarts=20)
+    _, _, rb = _conv_diff_run(max_restarts=20, orth="bcgs2_pyth")
+    assert ra.status == rb.status == "ok"
+    assert ra.s_hist == rb.s_hist
+    assert np.linalg.norm(ra.x - rb.x) <= 1e-9 * np.linalg.norm(ra.x)
