@@ -7,10 +7,13 @@ s_max = 32, restart 128).
 One step = one float64 solve plus one float32-IR solve of that system to
 ||b - A x|| / ||b|| <= 1e-10, with the matrix analysed and every input
 already resident in HBM; `value` is the float64 time with the column-wise
-Ritz pre-phase.  The same two solves with the pre-phase in adaptive
-monomial-basis blocks are timed too and reported beside it
-(fp64_monomial_prephase, fp32_ir_monomial_prephase).  Prints ONE JSON line
-(see keys below).
+Ritz pre-phase and the paper's BCGS2.  The same two solves are timed
+with the pre-phase in adaptive monomial-basis blocks
+(fp64_monomial_prephase, fp32_ir_monomial_prephase), with the Pythagorean
+second BCGS pass (fp64_pyth, fp32_ir_pyth) and with both
+(fp64_monomial_pyth, fp32_ir_monomial_pyth), and reported beside it, each
+with its speedup over the float64 default.  Prints ONE JSON line (see keys
+below).
 
 Roofline: the dominant kernel is the SELL SpMV of the matrix powers kernel
 (float64).  Its average launch duration comes from the HIP event pair the
@@ -125,10 +128,17 @@ def main():
     o32 = dict(o64, precision="fp32_ir", inner_tol=1e-6, max_outer=500)
     o64m = dict(o64, prephase="monomial", prephase_s=8)
     o32m = dict(o32, prephase="monomial", prephase_s=8)
+    o64p = dict(o64, orth="bcgs2_pyth")
+    o32p = dict(o32, orth="bcgs2_pyth")
+    o64mp = dict(o64m, orth="bcgs2_pyth")
+    o32mp = dict(o32m, orth="bcgs2_pyth")
     both = [("fp64", o64), ("fp32_ir", o32)]
     modes = {"both": both,
              "all": both + [("fp64_monomial_prephase", o64m),
-                            ("fp32_ir_monomial_prephase", o32m)],
+                            ("fp32_ir_monomial_prephase", o32m),
+                            ("fp64_pyth", o64p), ("fp32_ir_pyth", o32p),
+                            ("fp64_monomial_pyth", o64mp),
+                            ("fp32_ir_monomial_pyth", o32mp)],
              "fp64": [("fp64", o64)], "fp32_ir": [("fp32_ir", o32)]}[args.mode]
 
     if args.calibrate_copy_mb > 0:
@@ -205,7 +215,9 @@ def main():
     if "fp64" in per and "fp32_ir" in per:
         out["fp32_ir"]["speedup_vs_fp64"] = round(
             out["fp64"]["ms"] / out["fp32_ir"]["ms"], 3)
-    for name in ("fp64_monomial_prephase", "fp32_ir_monomial_prephase"):
+    for name in ("fp64_monomial_prephase", "fp32_ir_monomial_prephase",
+                 "fp64_pyth", "fp32_ir_pyth", "fp64_monomial_pyth",
+                 "fp32_ir_monomial_pyth"):
         if name in per and "fp64" in per:
             out[name]["speedup_vs_fp64"] = round(
                 out["fp64"]["ms"] / out[name]["ms"], 3)

@@ -221,14 +221,20 @@ void gemv_update(QView<const T> Q, const double* y, int k,
 
 // Fused Q(:, b0:b0+p) = V Zinv (in place, p = min(nc, *pcount)) and
 // R2 (ka x nc, ld ldr) = Q(:, 0:ka)^T Q(:, b0:b0+p) (columns >= p zero).
-// With gram, R2 is (ka + nc) x nc (ldr >= ka + nc): rows ka.. hold the Gram
-// of the new block on and above the diagonal 16 x 16 tiles (zero below).
 // Returns false (and does nothing) for shapes it does not cover (float32,
 // ka > 64, nc > 32 or nc < 2); the caller then runs trsm_inv + gemm_tn.
 template <typename T>
 bool trsm_proj(QView<T> Q, int ka, int b0, int nc, const double* Zinv,
                int ldz, const int* pcount, int64_t nrows, double* R2, int ldr,
-               Partials& P, hipStream_t st, bool gram = false);
+               Partials& P, hipStream_t st);
+
+// trsm_inv plus the Gram of the result, G (s x s, ld ldg, symmetric) =
+// Q(:, b0:b0+p)^T Q(:, b0:b0+p), zero outside p = min(s, *pcount).  Returns
+// false (and does nothing) beyond 64 columns.
+template <typename T>
+bool trsm_inv_gram(QView<T> Q, int b0, int s, const double* Rinv, int ldr,
+                   const int* pcount, int64_t nrows, double* G, int ldg,
+                   Partials& P, hipStream_t st);
 
 // Second pass of the Pythagorean BCGS2 variant in one pass over the block:
 // Q(:, b0:b0+p) = (Q(:, b0:b0+p) - Q(:, 0:ka) M(0:ka, 0:p)) Zinv(0:p, 0:p),

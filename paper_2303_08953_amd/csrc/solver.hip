@@ -191,13 +191,19 @@ void orth_block(QView<T> Q, int64_t nrows, int nb, int s, double omega,
   pchol_ice(w.G, w.lds, s, nullptr, omega, w.Z, w.Zinv, w.lds, p1,
             w.pchol_scr, st);
   if (pyth) {
-    // Pythagorean second pass: Q_1 = V Zinv, and [R2; Gk] = [Q Q_1]^T Q_1
-    // in one (nb + s) x s output (the Gram of Q_1 from the same pass);
-    // G2 = Gk - R2^T R2; then (Q_1 - Q R2) Zt^{-1} in one pass.
+    // Pythagorean second pass: Q_1 = V Zinv with its Gram Gk from the
+    // same registers, R2 = Q^T Q_1, stored as [R2; Gk] ((nb + s) x s, ld
+    // ldw); G2 = Gk - R2^T R2; then (Q_1 - Q R2) Zt^{-1} in one pass.
+    // Beyond 64 columns the Gram comes from one wider product instead.
+    // (Fusing the projection into the triangular solve, as the classical
+    // path does, measured slower here: the extra Gram accumulators cost
+    // the kernel its occupancy.)
     if (w.ldw < nb + s)
       throw Error{SGM_EINVAL, "orth_block: R2 workspace too short"};
-    if (!trsm_proj<T>(Q, nb, nb, s, w.Zinv, w.lds, p1, nrows, w.R2, w.ldw,
-                      w.P, st, true)) {
+    if (trsm_inv_gram<T>(Q, nb, s, w.Zinv, w.lds, p1, nrows, w.R2 + nb,
+                         w.ldw, w.P, st)) {
+      gemm_tn<T>(Qc, 0, nb, nb, s, p1, nrows, w.R2, w.ldw, w.P, st);
+    } else {
       trsm_inv<T>(Q, nb, s, w.Zinv, w.lds, p1, nrows, st);
       gemm_tn<T>(Qc, 0, nb + s, nb, s, p1, nrows, w.R2, w.ldw, w.P, st);
     }

@@ -524,13 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_update(
 // (q, t) needs in lane group g; the matching A operand, column
 // 16 i + c16 of Q at those MT rows, is one MT-vector load.
 // Requires ka <= 16 * MQ (MQ column tiles of Q accumulate in registers).
-// With GK the Gram Q_k^T Q_k is accumulated as well, from the same
-// registers (in the result layout, register q of tile j is the MFMA operand
-// for column 16 j + c16 over the rows of step (q, t), for both sides of a
-// T^T T product), and the partial holds the (ka + nc) x nc matrix
-// [Q(:, 0:ka) Q_k]^T Q_k: rows ka.. are the Gram, written for the tiles on
-// and above the diagonal (zeros below).
-template <typename T, int NT, int MT, int MQ, bool GK>
+template <typename T, int NT, int MT, int MQ>
 __global__ __launch_bounds__(kBlock) void k_trsm_proj(
     QView<T> Q, int ka, int b0c, int nc, const double* __restrict__ Zinv,
     int ldz, const int* __restrict__ pcount, int64_t nrows,
@@ -567,10 +561,6 @@ __global__ __launch_bounds__(kBlock) void k_trsm_proj(
   for (int i = 0; i < MQ; ++i)
 #pragma unroll
     for (int j = 0; j < NT; ++j) r2[i][j] = vzero<V>();
-  constexpr int NG = GK ? NT * (NT + 1) / 2 : 0;
-  V gk[NG > 0 ? NG : 1];
-#pragma unroll
-  for (int t = 0; t < (NG > 0 ? NG : 1); ++t) gk[t] = vzero<V>();
 
   for (int64_t rb = blockIdx.x; rb < nblocks; rb += gridDim.x) {
     const int64_t r0 = rb * rows_per_block + wave * rows_per_wave;
@@ -627,44 +617,30 @@ __global__ __launch_bounds__(kBlock) void k_trsm_proj(
           for (int j = 0; j < NT; ++j)
             r2[i][j] = mfma(qa[q][t], acc[t][j][q], r2[i][j]);
     }
-    if constexpr (GK) {
-      int tix = 0;
-#pragma unroll
-      for (int j1 = 0; j1 < NT; ++j1)
-#pragma unroll
-        for (int j2 = j1; j2 < NT; ++j2) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int t = 0; t < MT; ++t)
-              gk[tix] = mfma(acc[t][j1][q], acc[t][j2][q], gk[tix]);
-          ++tix;
-        }
-    }
   }
   // fixed-order sum of the four wavefronts through LDS, then one partial
   // per workgroup
   __syncthreads();
   double* red = reinterpret_cast<double*>(smem_raw);
-  constexpr int NR = MQ * NT;  // projection tiles, then the Gram tiles
+  constexpr int NE = MQ * NT * 4;
   for (int w = kBlock / kWave - 1; w >= 1; --w) {
     if (wave == w) {
 #pragma unroll
-      for (int x = 0; x < NR + NG; ++x)
+      for (int i = 0; i < MQ; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e = (x * 4 + q) * kWave + lane;
-          double v = (double)(x < NR ? r2[x / NT][x % NT][q]
-                                     : gk[(x - NR) % (NG > 0 ? NG : 1)][q]);
-          if (w < kBlock / kWave - 1) v += red[e];
-          red[e] = v;
-        }
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int e = ((i * NT + j) * 4 + q) * kWave + lane;
+            double v = (double)r2[i][j][q];
+            if (w < kBlock / kWave - 1) v += red[e];
+            red[e] = v;
+          }
     }
     __syncthreads();
   }
   if (wave == 0) {
-    const int ldo = GK ? ka + nc : ka;
-    double* out = part + (int64_t)blockIdx.x * ldo * nc;
+    double* out = part + (int64_t)blockIdx.x * ka * nc;
 #pragma unroll
     for (int i = 0; i < MQ; ++i)
 #pragma unroll
@@ -675,32 +651,10 @@ __global__ __launch_bounds__(kBlock) void k_trsm_proj(
           const int row = i * 16 + drow<T>(g, q);
           const int col = j * 16 + c16;
           if (row < ka && col < nc)
-            out[(int64_t)col * ldo + row] = (double)r2[i][j][q] + red[e];
+            out[(int64_t)col * ka + row] = (double)r2[i][j][q] + red[e];
         }
-    if constexpr (GK) {
-      int tix = 0;
-#pragma unroll
-      for (int j1 = 0; j1 < NT; ++j1)
-#pragma unroll
-        for (int j2 = 0; j2 < NT; ++j2) {
-          const bool upper = j2 >= j1;
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int row = j1 * 16 + drow<T>(g, q);
-            const int col = j2 * 16 + c16;
-            if (row < nc && col < nc) {
-              double v = 0.0;
-              if (upper) {
-                const int e = ((NR + tix) * 4 + q) * kWave + lane;
-                v = (double)gk[tix][q] + red[e];
-              }
-              out[(int64_t)col * ldo + ka + row] = v;
-            }
-          }
-          if (upper) ++tix;
-        }
-    }
   }
+  (void)NE;
 }
 
 // Second pass of the Pythagorean BCGS2 variant, update and triangular
@@ -1230,6 +1184,38 @@ void trsm_inv(QView<T> Q, int b0, int s, const double* Rinv, int ldr,
 }
 
 template <typename T>
+bool trsm_inv_gram(QView<T> Q, int b0, int s, const double* Rinv, int ldr,
+                   const int* pcount, int64_t nrows, double* G, int ldg,
+                   Partials& P, hipStream_t st) {
+  const int nt = (s + 15) / 16;
+  if (s <= 0 || nt > 4) return false;
+  if (sizeof(T) == 4 && nt <= 2) {
+    if (nt == 1)
+      launch_update<T, 1, 2, MODE_TRSM, true>(Q, 0, s, b0, s, Rinv, ldr,
+                                              pcount, nrows, G, ldg, P, st,
+                                              1024);
+    else
+      launch_update<T, 2, 2, MODE_TRSM, true>(Q, 0, s, b0, s, Rinv, ldr,
+                                              pcount, nrows, G, ldg, P, st,
+                                              1024);
+    return true;
+  }
+  if (nt == 1)
+    launch_update<T, 1, 4, MODE_TRSM, true>(Q, 0, s, b0, s, Rinv, ldr, pcount,
+                                            nrows, G, ldg, P, st);
+  else if (nt == 2)
+    launch_update<T, 2, 4, MODE_TRSM, true>(Q, 0, s, b0, s, Rinv, ldr, pcount,
+                                            nrows, G, ldg, P, st);
+  else if (nt == 3)
+    launch_update<T, 3, 2, MODE_TRSM, true>(Q, 0, s, b0, s, Rinv, ldr, pcount,
+                                            nrows, G, ldg, P, st);
+  else
+    launch_update<T, 4, 2, MODE_TRSM, true>(Q, 0, s, b0, s, Rinv, ldr, pcount,
+                                            nrows, G, ldg, P, st);
+  return true;
+}
+
+template <typename T>
 void gemv_update(QView<const T> Q, const double* y, int k,
                  const double* sdev, double* x, int64_t n, hipStream_t st) {
   if (k <= 0) return;
@@ -1241,27 +1227,25 @@ void gemv_update(QView<const T> Q, const double* y, int k,
 }
 
 namespace {
-template <typename T, int NT, int MQ, bool GK>
+template <typename T, int NT, int MQ>
 void launch_trsm_proj(QView<T> Q, int ka, int b0, int nc, const double* Zinv,
                       int ldz, const int* pcount, int64_t nrows, double* R2,
                       int ldr, Partials& P, hipStream_t st) {
   constexpr int MT = 4;
-  const int ldo = GK ? ka + nc : ka;
   const int64_t rows_per_block = 16 * MT * (kBlock / kWave);
   const int64_t nblocks = ceil_div(nrows, rows_per_block);
   int64_t grid = nblocks < kTargetGroups ? nblocks : kTargetGroups;
   if (grid < 1) grid = 1;
-  if (grid * ldo * nc > P.cap) grid = P.cap / ((int64_t)ldo * nc);
+  if (grid * ka * nc > P.cap) grid = P.cap / ((int64_t)ka * nc);
   if (grid < 1) throw Error{SGM_EINVAL, "partial scratch too small"};
   const size_t stage = (size_t)(((nc + 3) & ~3)) * NT * 16 * sizeof(T);
-  const int ng = GK ? NT * (NT + 1) / 2 : 0;
-  const size_t red = (size_t)(MQ * NT + ng) * 4 * kWave * sizeof(double);
+  const size_t red = (size_t)MQ * NT * 4 * kWave * sizeof(double);
   const size_t lds = stage > red ? stage : red;
-  hipLaunchKernelGGL((k_trsm_proj<T, NT, MT, MQ, GK>), dim3((unsigned)grid),
+  hipLaunchKernelGGL((k_trsm_proj<T, NT, MT, MQ>), dim3((unsigned)grid),
                      dim3(kBlock), lds, st, Q, ka, b0, nc, Zinv, ldz, pcount,
                      nrows, P.buf);
   SGM_CHECK_LAUNCH();
-  launch_reduce(P.buf, grid, ldo, nc, R2, ldr, 0, st);
+  launch_reduce(P.buf, grid, ka, nc, R2, ldr, 0, st);
 }
 }  // namespace
 
@@ -1273,19 +1257,13 @@ void launch_trsm_proj(QView<T> Q, int ka, int b0, int nc, const double* Zinv,
 template <typename T>
 bool trsm_proj(QView<T> Q, int ka, int b0, int nc, const double* Zinv,
                int ldz, const int* pcount, int64_t nrows, double* R2, int ldr,
-               Partials& P, hipStream_t st, bool gram) {
+               Partials& P, hipStream_t st) {
   if (sizeof(T) != 8 || ka < 1 || nc < 2 || ka > 64 || nc > 32) return false;
-  if (gram && ldr < ka + nc)
-    throw Error{SGM_EINVAL, "trsm_proj: output too short for the Gram rows"};
   const int nt = (nc + 15) / 16, mq = (ka + 15) / 16;
 #define SGM_TP(NTv, MQv)                                                      \
   if (nt == NTv && mq <= MQv) {                                               \
-    if (gram)                                                                 \
-      launch_trsm_proj<T, NTv, MQv, true>(Q, ka, b0, nc, Zinv, ldz, pcount,   \
-                                          nrows, R2, ldr, P, st);             \
-    else                                                                      \
-      launch_trsm_proj<T, NTv, MQv, false>(Q, ka, b0, nc, Zinv, ldz, pcount,  \
-                                           nrows, R2, ldr, P, st);            \
+    launch_trsm_proj<T, NTv, MQv>(Q, ka, b0, nc, Zinv, ldz, pcount, nrows,    \
+                                  R2, ldr, P, st);                            \
     return true;                                                              \
   }
   SGM_TP(1, 2) SGM_TP(1, 4)
@@ -1411,6 +1389,9 @@ void col_scale(QView<T> Q, int vcol, const double* z, const int* pmask,
                                Partials&, hipStream_t);                      \
   template void trsm_inv<T>(QView<T>, int, int, const double*, int,          \
                             const int*, int64_t, hipStream_t);               \
+  template bool trsm_inv_gram<T>(QView<T>, int, int, const double*, int,     \
+                                 const int*, int64_t, double*, int,          \
+                                 Partials&, hipStream_t);                    \
   template void gemv_update<T>(QView<const T>, const double*, int,           \
                                const double*, double*, int64_t, hipStream_t); \
   template void col_dots<T>(QView<const T>, int, int, const int*, int64_t,   \
@@ -1421,7 +1402,7 @@ void col_scale(QView<T> Q, int vcol, const double* z, const int* pmask,
                              int64_t, hipStream_t);                          \
   template bool trsm_proj<T>(QView<T>, int, int, int, const double*, int,    \
                              const int*, int64_t, double*, int, Partials&,   \
-                             hipStream_t, bool);                             \
+                             hipStream_t);                                   \
   template void update_trsm<T>(QView<T>, int, int, int, const double*, int,  \
                                const double*, int, const int*, int64_t,      \
                                hipStream_t);

@@ -1,11 +1,11 @@
 """GPU parity of the Pythagorean BCGS2 variant (orth="bcgs2_pyth") against
 the oracle's block_orth(pythagorean=True) and solve(orth="bcgs2_pyth").
 
-Block shapes reach every kernel path of the variant's second pass:
-- float64 with at most 64 prior columns and 2..32 new ones: the triangular
-  solve, projection and Gram fused in one pass;
-- more prior columns, or float32: triangular solve, then [Q Q_1]^T Q_1 as
-  one tall-skinny product;
+Block shapes reach every kernel path of the variant's second pass, in
+float64 and float32:
+- up to 64 new columns: the triangular solve with the Gram of its result
+  in the same pass, then the projection; beyond 64, the triangular solve,
+  then [Q Q_1]^T Q_1 as one wider product;
 - the fused update + triangular solve for 1..4 column tiles, and the
   two-pass fallback beyond 64 columns;
 - a truncating Krylov block (p < s) and a block almost inside span(Q),
