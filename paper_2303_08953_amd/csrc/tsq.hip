@@ -859,34 +859,52 @@ __global__ __launch_bounds__(256) void k_pyth_gram(
   }
 }
 
-// x(r) += scale * sum_j Q(r, j) y(j), j < k (float64 accumulation).  A
-// wavefront's 64 consecutive rows read 64 contiguous elements per column.
+// x(r) += scale * sum_j Q(r, j) y(j), j < k (float64 accumulation, columns
+// summed in order).  A wavefront takes 128 rows: lane l reads rows 2l and
+// 2l + 1 of its half's 64-row panel as one 2-vector per column, and eight
+// columns of loads are issued before their products (a read stream of
+// k + 1 columns; one lane-row per thread held the kernel to ~4.9 TB/s).
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemv_update(
     QView<const T> Q, const double* __restrict__ y, int k,
     const double* __restrict__ sdev, double* __restrict__ x, int64_t n) {
+  typedef T T2 __attribute__((ext_vector_type(2)));
   __shared__ double ys[1024];
   const double sc = sdev ? sdev[0] : 1.0;
   const int64_t cs = Q.cstride;
+  const int lane = threadIdx.x % kWave;
+  const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / kWave) +
+                        threadIdx.x / kWave;
+  const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
   for (int base = 0; base < k; base += 1024) {
+    const int kk = min(1024, k - base);
     __syncthreads();
-    for (int j = threadIdx.x; j < 1024 && base + j < k; j += blockDim.x)
-      ys[j] = y[base + j];
+    for (int j = threadIdx.x; j < kk; j += blockDim.x) ys[j] = y[base + j];
     __syncthreads();
-    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < n;
-         r += (int64_t)gridDim.x * blockDim.x) {
-      double acc = 0.0;
-      const int kk = min(1024, k - base);
-      const T* q = Q.base + Q.row_off(r) + (int64_t)base * cs;
+    for (int64_t wv = wave0; wv * 128 < n; wv += nwaves) {
+      const int64_t r0 = wv * 128 + 2 * lane;  // r0 and r0 + 1: one panel
+      if (r0 >= n) continue;
+      const T* q = Q.base + Q.row_off(r0) + (int64_t)base * cs;
+      double a0 = 0.0, a1 = 0.0;
       int j = 0;
-      for (; j + 4 <= kk; j += 4) {
-        acc += (double)q[(int64_t)j * cs] * ys[j];
-        acc += (double)q[(int64_t)(j + 1) * cs] * ys[j + 1];
-        acc += (double)q[(int64_t)(j + 2) * cs] * ys[j + 2];
-        acc += (double)q[(int64_t)(j + 3) * cs] * ys[j + 3];
+      for (; j + 8 <= kk; j += 8) {
+        T2 v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+          v[t] = *reinterpret_cast<const T2*>(q + (int64_t)(j + t) * cs);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          a0 += (double)v[t][0] * ys[j + t];
+          a1 += (double)v[t][1] * ys[j + t];
+        }
       }
-      for (; j < kk; ++j) acc += (double)q[(int64_t)j * cs] * ys[j];
-      x[r] += sc * acc;
+      for (; j < kk; ++j) {
+        const T2 v = *reinterpret_cast<const T2*>(q + (int64_t)j * cs);
+        a0 += (double)v[0] * ys[j];
+        a1 += (double)v[1] * ys[j];
+      }
+      x[r0] += sc * a0;
+      if (r0 + 1 < n) x[r0 + 1] += sc * a1;
     }
   }
 }
@@ -1219,8 +1237,8 @@ template <typename T>
 void gemv_update(QView<const T> Q, const double* y, int k,
                  const double* sdev, double* x, int64_t n, hipStream_t st) {
   if (k <= 0) return;
-  int64_t grid = ceil_div(n, 256);
-  if (grid > 4096) grid = 4096;
+  int64_t grid = ceil_div(n, 4 * 128);  // four 128-row wavefronts per group
+  if (grid > 8192) grid = 8192;
   hipLaunchKernelGGL(k_gemv_update<T>, dim3((unsigned)grid), dim3(256), 0,
                      st, Q, y, k, sdev, x, n);
   SGM_CHECK_LAUNCH();
