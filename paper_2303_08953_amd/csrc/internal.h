@@ -271,6 +271,10 @@ void col_scale(QView<T> Q, int vcol, const double* z, const int* pmask,
 enum Ctrl {
   C_P1 = 0, C_P2, C_PH, C_BREAK, C_KDONE, C_CONV, C_BAD, C_NCTRL
 };
+// Device-only word after the control block: set by a block tail that ends
+// a cycle (convergence, breakdown or a non-finite estimate) when the host
+// has queued further steps without waiting; later tails then do nothing.
+constexpr int C_STOP = C_NCTRL;
 
 void pchol_ice(const double* G, int ldg, int smax, const int* s_dev,
                double omega, double* R, double* Rinv, int ldr, int* p_out,
@@ -284,7 +288,9 @@ void combine_r(const double* W, int ldw, const double* R2, int ldr2,
 // Rtop / Rkk (may be NULL) receive R(1:nb, k) (ld ldw) and R(k, k) (ld ldz).
 // res_out receives the per-column residual estimates and host_ctrl (may be
 // NULL) a copy of the control words; both may point into host memory
-// mapped for the device, so the host reads them without a copy.
+// mapped for the device, so the host reads them without a copy.  stop (may
+// be NULL, device): when *stop is set the tail does nothing; a tail that
+// ends the cycle sets it (for steps queued ahead of the host's checks).
 size_t block_tail_scratch_doubles(int nb_max, int s_max);
 void block_tail(const double* W, const double* R2, int ldw, const double* Z,
                 const double* Zt, const double* Zi, const double* Zti, int ldz,
@@ -292,7 +298,7 @@ void block_tail(const double* W, const double* R2, int ldw, const double* Z,
                 double* Hr, int ldh, double* cs, double* sn, double* g,
                 const double* rec, int n_rec, const double* beta0, double tol,
                 double* res_out, int* host_ctrl, double* scratch,
-                hipStream_t st);
+                hipStream_t st, int* stop = nullptr);
 void back_solve(const double* Hr, int ldh, const double* g, const int* kdev,
                 int kmax, double* y, hipStream_t st);
 void givens_init(double* g, int m, const double* beta, hipStream_t st);

@@ -401,7 +401,7 @@ __device__ __forceinline__ void tail_body(
     double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
     const double* __restrict__ rec, int n_rec,
     const double* __restrict__ beta0, double tol,
-    double* __restrict__ res_out, int* __restrict__ host_ctrl) {
+    double* __restrict__ res_out, int* __restrict__ host_ctrl, int* stop) {
   int& kdone_s = sh[0];
   int& conv_s = sh[1];
   int& bad_s = sh[2];
@@ -614,6 +614,7 @@ __device__ __forceinline__ void tail_body(
     // the control words the host needs, straight into its mapped memory
     if (host_ctrl)
       for (int k = 0; k < C_NCTRL; ++k) host_ctrl[k] = ctrl[k];
+    if (stop && (brk || conv_s || bad_s)) *stop = 1;
   }
 }
 
@@ -627,18 +628,21 @@ __global__ __launch_bounds__(kSmallBlock) void k_block_tail(
     double* __restrict__ sn, double* __restrict__ g,
     const double* __restrict__ rec, int n_rec,
     const double* __restrict__ beta0, double tol, double* __restrict__ res_out,
-    int* __restrict__ host_ctrl, double* scratch) {
+    int* __restrict__ host_ctrl, double* scratch, int* stop) {
   __shared__ double lds[kTailLds];
   __shared__ int sh[4];
+  // a queued step after the end of the cycle: leave every state untouched
+  // (the flag was written by an earlier kernel of the stream)
+  if (stop && *stop) return;
   const int p = ctrl[C_P2] == 0 ? 1 : ctrl[C_P2];
   if (tail_doubles(nb, p) <= (size_t)kTailLds)
     tail_body(lds, sh, W, R2g, ldw, Zg, Ztg, Zig, Ztig, ldz, nb, ctrl,
               Rtop_out, Rkk_out, Hraw, Hr, ldh, cs, sn, g, rec, n_rec, beta0,
-              tol, res_out, host_ctrl);
+              tol, res_out, host_ctrl, stop);
   else
     tail_body(scratch, sh, W, R2g, ldw, Zg, Ztg, Zig, Ztig, ldz, nb, ctrl,
               Rtop_out, Rkk_out, Hraw, Hr, ldh, cs, sn, g, rec, n_rec, beta0,
-              tol, res_out, host_ctrl);
+              tol, res_out, host_ctrl, stop);
 }
 
 // y = Hr(0:k, 0:k)^{-1} g(0:k), column-oriented back substitution.
@@ -757,11 +761,11 @@ void block_tail(const double* W, const double* R2, int ldw, const double* Z,
                 double* Hr, int ldh, double* cs, double* sn, double* g,
                 const double* rec, int n_rec, const double* beta0, double tol,
                 double* res_out, int* host_ctrl, double* scratch,
-                hipStream_t st) {
+                hipStream_t st, int* stop) {
   hipLaunchKernelGGL(k_block_tail, dim3(1), dim3(kSmallBlock), 0, st, W, R2,
                      ldw, Z, Zt, Zi, Zti, ldz, nb, ctrl, Rtop, Rkk, Hraw, Hr,
                      ldh, cs, sn, g, rec, n_rec, beta0, tol, res_out,
-                     host_ctrl, scratch);
+                     host_ctrl, scratch, stop);
   SGM_CHECK_LAUNCH();
 }
 

@@ -119,7 +119,18 @@ struct HostMirror {
   double* scal = nullptr;
   int* dctrl = nullptr;     // device views of the same bytes
   double* dres = nullptr;
+  // one slot per queued column-wise step (control words, residual estimate)
+  int* slot_ctrl = nullptr;
+  double* slot_res = nullptr;
+  int* dslot_ctrl = nullptr;
+  double* dslot_res = nullptr;
 };
+constexpr size_t kSlotCtrlOff = 32 * 1024;  // kMaxSlots x kSlotInts ints
+constexpr int kSlotInts = 8;
+constexpr int kMaxSlots = 256;
+constexpr size_t kSlotResOff =
+    kSlotCtrlOff + sizeof(int) * kSlotInts * kMaxSlots;  // kMaxSlots doubles
+static_assert(C_NCTRL <= kSlotInts, "control words do not fit a slot");
 
 // Wait for the stream by polling: a blocking synchronisation sleeps and
 // wakes up tens of microseconds late, once per block.
@@ -403,6 +414,44 @@ struct Engine {
     return b;
   }
 
+  // The column-wise pre-phase steps 1..nsteps (s = 1, monomial), queued
+  // back to back with one host synchronisation at the end: every step's
+  // tail writes its control words and estimate into its own slot of the
+  // mapped host memory, and the tail that ends the cycle (convergence,
+  // breakdown, non-finite estimate) sets the device stop word, after which
+  // the queued tails leave the Hessenberg and Givens state untouched (the
+  // other kernels of those steps only touch columns the cycle no longer
+  // uses).  Returns the slots' control words in order.
+  std::vector<BlockOut> column_steps(int nsteps, const double* beta0,
+                                     double tol) {
+    SGM_HIP(hipMemsetAsync(w.ctrl + C_STOP, 0, sizeof(int), st));
+    for (int t = 0; t < nsteps; ++t) {
+      const int nbt = 1 + t;
+      spmv_mpk<T>(S, vals, Q(), nbt - 1, -1, nbt, w.mono, 0, st);
+      orth_block<T>(Q(), ld, nbt, 1, omega, w, st, false);
+      block_tail(w.W, w.R2, w.ldw, w.Z, w.Zt, w.Zinv, w.Ztinv, w.lds, nbt,
+                 w.ctrl, nullptr, nullptr, w.Hraw, w.Hr, w.ldh, w.cs, w.sn,
+                 w.g, w.mono, 1, beta0, tol, hm.dslot_res + t,
+                 hm.dslot_ctrl + (size_t)kSlotInts * t, w.tail_scr, st,
+                 w.ctrl + C_STOP);
+    }
+    wait_stream(st);
+    std::vector<BlockOut> out;
+    for (int t = 0; t < nsteps; ++t) {
+      const int* c = hm.slot_ctrl + (size_t)kSlotInts * t;
+      BlockOut b;
+      b.p2 = c[C_P2];
+      b.ph = c[C_PH];
+      b.brk = c[C_BREAK];
+      b.kdone = c[C_KDONE];
+      b.conv = c[C_CONV];
+      b.bad = c[C_BAD];
+      out.push_back(b);
+      if (b.bad || b.brk || b.conv || b.p2 == 0) break;
+    }
+    return out;
+  }
+
   // One restart cycle from Q(:, 0) (already the normalised residual) with
   // g = beta_dev e_1.  Returns the number of Hessenberg columns and leaves
   // y in w.y.  res_scale converts the estimates to the caller's reference.
@@ -421,6 +470,29 @@ struct Engine {
                     : 1;
     auto t_pre = Clock::now();
     bool timing_pre = !sh.known;
+    if (!sh.known && s_pre == 1 && m0 >= 1 && m0 <= kMaxSlots) {
+      // the column-wise pre-phase, queued without per-step synchronisation
+      const std::vector<BlockOut> bs =
+          column_steps(m0, beta0_dev, prephase_only ? -1.0 : tol);
+      for (size_t t = 0; t < bs.size(); ++t) {
+        const BlockOut& b = bs[t];
+        if (b.bad) throw Error{SGM_ENUMERIC, "non-finite residual estimate"};
+        if (!prephase_only) {
+          // one column per step: kdone is 0 or 1
+          if (b.kdone > 0) res.res_hist.push_back(hm.slot_res[t] * res_scale);
+          res.s_hist.push_back(b.brk ? 0 : b.p2);
+          if (b.kdone > 0) res.rel_est = hm.slot_res[t] * res_scale;
+        }
+        k = nb - 1 + b.kdone;
+        if (b.brk) {
+          conv = true;
+          break;
+        }
+        if (b.conv) conv = true;
+        nb += b.p2;
+        if (conv) break;
+      }
+    }
     while (nb <= last && !conv) {
       if (!sh.known && nb > m0) {
         compute_shifts(nb - 1);
@@ -478,6 +550,14 @@ void run_solve(Handle* h, const double* b, const double* x0, double* x,
   hm.scal = reinterpret_cast<double*>(static_cast<char*>(h->pinned) + 128);
   hm.dctrl = static_cast<int*>(h->pinned_dev);
   hm.dres = reinterpret_cast<double*>(static_cast<char*>(h->pinned_dev) + 256);
+  hm.slot_ctrl = reinterpret_cast<int*>(static_cast<char*>(h->pinned) +
+                                        kSlotCtrlOff);
+  hm.slot_res = reinterpret_cast<double*>(static_cast<char*>(h->pinned) +
+                                          kSlotResOff);
+  hm.dslot_ctrl = reinterpret_cast<int*>(static_cast<char*>(h->pinned_dev) +
+                                         kSlotCtrlOff);
+  hm.dslot_res = reinterpret_cast<double*>(
+      static_cast<char*>(h->pinned_dev) + kSlotResOff);
   const double* v64 = S.val64;
   const float* v32 = S.val32;
   if (jac) {
