@@ -251,15 +251,20 @@ void pyth_gram(const double* C, int ldc, int ka, int nc, const int* pcount,
                double* G2, int ldg, hipStream_t st);
 
 // One-column blocks (s = 1), nrows a multiple of the 64-row panel:
-// C(0:ma) = Q(:, 0:ma)^T v with v = Q(:, vcol); pmask (device, may be
-// NULL): zero result when *pmask == 0.
+// C(0:ma) = Q(:, 0:ma)^T v with v = Q(:, vcol), times *dscale
+// when given; pmask (device, may be NULL): zero result when *pmask == 0.
 template <typename T>
 void col_dots(QView<const T> Q, int ma, int vcol, const int* pmask,
-              int64_t nrows, double* C, Partials& P, hipStream_t st);
-// v -= Q(:, 0:ma) w and *G = v^T v (pmask as above).
+              const double* dscale, int64_t nrows, double* C, Partials& P,
+              hipStream_t st);
+// v = v * (*vscale) - Q(:, 0:ma) w (vscale may be NULL: no scaling), then
+// Alg. 3 on the 1 x 1 Gram g = v^T v: *p_out = 1, R[0] = sqrt(g),
+// Rinv[0] = 1 / R[0] when g > 0 is finite, else 0 and R, Rinv untouched.
+// With *pmask == 0 (pmask may be NULL) nothing changes and *p_out = 0.
 template <typename T>
 void col_update(QView<T> Q, int ma, int vcol, const double* w,
-                const int* pmask, int64_t nrows, double* G, Partials& P,
+                const double* vscale, const int* pmask, int64_t nrows,
+                double* R, double* Rinv, int* p_out, Partials& P,
                 hipStream_t st);
 // v *= *z when *pmask > 0.
 template <typename T>

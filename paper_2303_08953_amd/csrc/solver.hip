@@ -178,16 +178,15 @@ void orth_block(QView<T> Q, int64_t nrows, int nb, int s, double omega,
   int* p1 = w.ctrl + C_P1;
   int* p2 = w.ctrl + C_P2;
   if (s == 1) {
-    // one column: the same steps with column-wise kernels
-    col_dots<T>(Qc, nb, nb, nullptr, nrows, w.W, w.P, st);
-    col_update<T>(Q, nb, nb, w.W, nullptr, nrows, w.G, w.P, st);
-    pchol_ice(w.G, w.lds, 1, nullptr, omega, w.Z, w.Zinv, w.lds, p1,
-              w.pchol_scr, st);
-    col_scale<T>(Q, nb, w.Zinv, p1, nrows, st);
-    col_dots<T>(Qc, nb, nb, p1, nrows, w.R2, w.P, st);
-    col_update<T>(Q, nb, nb, w.R2, p1, nrows, w.G2, w.P, st);
-    pchol_ice(w.G2, w.lds, 1, p1, omega, w.Zt, w.Ztinv, w.lds, p2,
-              w.pchol_scr, st);
+    // One column (CGS2).  The first normalisation v / r1 is not stored: the
+    // second projection is taken as (Q^T v) / r1 and the second update
+    // scales v on the way.  With a scalar r1 this changes only the rounding.
+    col_dots<T>(Qc, nb, nb, nullptr, nullptr, nrows, w.W, w.P, st);
+    col_update<T>(Q, nb, nb, w.W, nullptr, nullptr, nrows, w.Z, w.Zinv, p1,
+                  w.P, st);
+    col_dots<T>(Qc, nb, nb, p1, w.Zinv, nrows, w.R2, w.P, st);
+    col_update<T>(Q, nb, nb, w.R2, w.Zinv, p1, nrows, w.Zt, w.Ztinv, p2, w.P,
+                  st);
     col_scale<T>(Q, nb, w.Ztinv, p2, nrows, st);
     if (combine)
       combine_r(w.W, w.ldw, w.R2, w.ldw, w.Z, w.Zt, w.lds, nb, w.ctrl, w.Rtop,

@@ -969,13 +969,15 @@ __global__ __launch_bounds__(kBlock) void k_col_dots(
 }
 
 // v = Q(:, vcol) -= Q(:, 0:ma) w (w float64, rounded to T like the MFMA
-// update stages it) and part[chunk] = sum of the new v(r)^2 over the
-// chunk's rows.  With *pmask == 0 nothing changes and the sums are zero.
+// update stages it), after v *= *vscale when vscale is given (a previous
+// normalisation applied on the way), and part[chunk] = sum of the new
+// v(r)^2 over the chunk's rows.  With *pmask == 0 nothing changes and the
+// sums are zero.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_col_update(
     QView<T> Q, int ma, int vcol, const double* __restrict__ w,
-    const int* __restrict__ pmask, int64_t npanels, int chunks,
-    double* __restrict__ part) {
+    const double* __restrict__ vscale, const int* __restrict__ pmask,
+    int64_t npanels, int chunks, double* __restrict__ part) {
   extern __shared__ char smem_raw[];
   T* ws = reinterpret_cast<T*>(smem_raw);
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
@@ -986,11 +988,13 @@ __global__ __launch_bounds__(kBlock) void k_col_update(
   const bool live = pmask == nullptr || *pmask > 0;
   for (int j = threadIdx.x; j < ma; j += kBlock) ws[j] = (T)w[j];
   __syncthreads();
+  const T sc = (live && vscale) ? (T)vscale[0] : (T)1;
   double ss = 0.0;
   if (live) {
     for (int64_t pp = p0 + wave; pp < p1; pp += kBlock / kWave) {
       T* rb = Q.base + Q.row_off(pp * kPanel) + lane;
       T v = rb[(int64_t)vcol * Q.cstride];
+      if (vscale) v = v * sc;
       int j = 0;
       for (; j + 8 <= ma; j += 8) {
         T q[8];
@@ -1005,13 +1009,73 @@ __global__ __launch_bounds__(kBlock) void k_col_update(
     }
   }
   for (int off = kWave / 2; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
-  __shared__ double red[kBlock / kWave];
-  if (lane == 0) red[wave] = ss;
+  __shared__ double red1[kBlock / kWave];
+  if (lane == 0) red1[wave] = ss;
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t = red[0];
-    for (int k = 1; k < kBlock / kWave; ++k) t += red[k];
+    double t = red1[0];
+    for (int k = 1; k < kBlock / kWave; ++k) t += red1[k];
     part[chunk] = t;
+  }
+}
+
+// Fixed-order sum over the chunks of ne = ndots + norm partials (ndots dot
+// products, then with norm the square sum g).  Sixteen wavefronts split the
+// chunks, lane = output, as in k_reduce_chunks.  live = (pmask == NULL or
+// *pmask > 0).
+// - With norm: the partial Cholesky of the 1 x 1 Gram g (Alg. 3 with
+//   s = 1: the pivot alone decides, one column's condition estimate is 1):
+//   *p_out = 1, R[0] = sqrt(g), Rinv[0] = 1 / R[0] when live and g > 0 is
+//   finite, else *p_out = 0 and R, Rinv untouched.
+// - dots_out[0:ndots] = the dots times *dscale (when given), zero when not
+//   live.
+__global__ __launch_bounds__(kRedWaves * kWave) void k_col_finish(
+    const double* __restrict__ part, int64_t nchunks, int ndots, int norm,
+    const int* __restrict__ pmask, const double* __restrict__ dscale,
+    double* __restrict__ dots_out, double* __restrict__ R,
+    double* __restrict__ Rinv, int* p_out) {
+  __shared__ double red[kRedWaves][kWave];
+  __shared__ double gsum;
+  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int ne = ndots + norm;
+  const bool live = pmask == nullptr || *pmask > 0;
+  const double sc = (live && dscale) ? dscale[0] : 1.0;
+  for (int e0 = 0; e0 < ne; e0 += kWave) {
+    const int e = e0 + lane;
+    double s = 0.0;
+    if (e < ne) {
+      int64_t c = w;
+      for (; c + 7 * kRedWaves < nchunks; c += 8 * kRedWaves) {
+        double a[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] = part[(c + q * kRedWaves) * ne + e];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s += a[q];
+      }
+      for (; c < nchunks; c += kRedWaves) s += part[c * ne + e];
+    }
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && e < ne) {
+      double t = 0.0;
+      for (int q = 0; q < kRedWaves; ++q) t += red[q][lane];
+      if (e < ndots) {
+        if (dots_out) dots_out[e] = live ? t * sc : 0.0;
+      } else {
+        gsum = t;
+      }
+    }
+    __syncthreads();
+  }
+  if (norm && threadIdx.x == 0) {
+    const double g = gsum;
+    const bool ok = live && g > 0.0 && isfinite(g);
+    if (ok) {
+      const double r = sqrt(g);
+      R[0] = r;
+      Rinv[0] = 1.0 / r;
+    }
+    *p_out = ok ? 1 : 0;
   }
 }
 
@@ -1364,7 +1428,8 @@ constexpr int kColTile = 16;
 
 template <typename T>
 void col_dots(QView<const T> Q, int ma, int vcol, const int* pmask,
-              int64_t nrows, double* C, Partials& P, hipStream_t st) {
+              const double* dscale, int64_t nrows, double* C, Partials& P,
+              hipStream_t st) {
   if (ma <= 0) return;
   const int64_t npanels = nrows / kPanel;
   const int ctiles = (ma + kColTile - 1) / kColTile;
@@ -1373,20 +1438,29 @@ void col_dots(QView<const T> Q, int ma, int vcol, const int* pmask,
                      dim3(kBlock), 0, st, Q, ma, vcol, pmask, npanels, ctiles,
                      chunks, P.buf);
   SGM_CHECK_LAUNCH();
-  launch_reduce(P.buf, chunks, ma, 1, C, ma, 0, st);
+  hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(kRedWaves * kWave), 0, st,
+                     (const double*)P.buf, (int64_t)chunks, ma, 0, pmask,
+                     dscale, C, (double*)nullptr, (double*)nullptr,
+                     (int*)nullptr);
+  SGM_CHECK_LAUNCH();
 }
 
 template <typename T>
 void col_update(QView<T> Q, int ma, int vcol, const double* w,
-                const int* pmask, int64_t nrows, double* G, Partials& P,
+                const double* vscale, const int* pmask, int64_t nrows,
+                double* R, double* Rinv, int* p_out, Partials& P,
                 hipStream_t st) {
   const int64_t npanels = nrows / kPanel;
   const int chunks = col_chunks(npanels, 1, 1, P);
   const size_t lds = sizeof(T) * (size_t)(ma > 0 ? ma : 1);
   hipLaunchKernelGGL(k_col_update<T>, dim3(chunks), dim3(kBlock), lds, st, Q,
-                     ma, vcol, w, pmask, npanels, chunks, P.buf);
+                     ma, vcol, w, vscale, pmask, npanels, chunks, P.buf);
   SGM_CHECK_LAUNCH();
-  launch_reduce(P.buf, chunks, 1, 1, G, 1, 0, st);
+  hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(kRedWaves * kWave), 0, st,
+                     (const double*)P.buf, (int64_t)chunks, 0, 1, pmask,
+                     (const double*)nullptr, (double*)nullptr, R, Rinv,
+                     p_out);
+  SGM_CHECK_LAUNCH();
 }
 
 template <typename T>
@@ -1412,10 +1486,12 @@ void col_scale(QView<T> Q, int vcol, const double* z, const int* pmask,
                                  Partials&, hipStream_t);                    \
   template void gemv_update<T>(QView<const T>, const double*, int,           \
                                const double*, double*, int64_t, hipStream_t); \
-  template void col_dots<T>(QView<const T>, int, int, const int*, int64_t,   \
-                            double*, Partials&, hipStream_t);                \
-  template void col_update<T>(QView<T>, int, int, const double*, const int*, \
-                              int64_t, double*, Partials&, hipStream_t);     \
+  template void col_dots<T>(QView<const T>, int, int, const int*,            \
+                            const double*, int64_t, double*, Partials&,      \
+                            hipStream_t);                                    \
+  template void col_update<T>(QView<T>, int, int, const double*,             \
+                              const double*, const int*, int64_t, double*,   \
+                              double*, int*, Partials&, hipStream_t);        \
   template void col_scale<T>(QView<T>, int, const double*, const int*,       \
                              int64_t, hipStream_t);                          \
   template bool trsm_proj<T>(QView<T>, int, int, int, const double*, int,    \
