@@ -301,63 +301,58 @@ __global__ __launch_bounds__(kSmallBlock) void k_combine(
   }
 }
 
-// C(m x n) = (add ? C : 0) + alpha A(m x k) B(k x n), all column-major in
-// LDS or global memory, by the whole workgroup with 4 x 4 register tiles
-// (every A and B element feeds 4 multiply-adds from registers).  Thread t
-// takes rows rg, rg + RG, rg + 2 RG, rg + 3 RG (rg = t % RG, RG = the number
-// of row groups) so that neighbouring threads read neighbouring rows, and
-// columns 4 cg .. 4 cg + 3 (cg = t / RG).
-__device__ __forceinline__ void tile_gemm(int m, int n, int k,
-                                          const double* A, int lda,
-                                          const double* B, int ldb, double* C,
-                                          int ldc, double alpha, bool add) {
-  const int RG = (m + 3) / 4, CG = (n + 3) / 4;
-  for (int t = threadIdx.x; t < RG * CG; t += blockDim.x) {
-    const int rg = t % RG, c0 = (t / RG) * 4;
-    // out-of-range rows / columns read row / column 0 and are not stored
-    const double* ap[4];
-    const double* bp[4];
+// C(0:m, 0:n) = (add ? C : 0) + alpha A(0:m, 0:k) B(0:k, 0:n), column-major
+// operands in LDS or global memory, on the float64 matrix cores
+// (v_mfma_f64_16x16x4f64): the block's wavefronts take 16 x 16 output
+// tiles in turn; lane l supplies A(m0 + l % 16, k0 + l / 16) and
+// B(k0 + l / 16, n0 + l % 16) per 4-deep step (zero outside the operands)
+// and holds C(m0 + l / 16 + 4 j, n0 + l % 16) in result register j.  Each
+// output is a fixed-order sum over k.
+__device__ __forceinline__ void tile_gemm_mfma(int m, int n, int k,
+                                               const double* A, int lda,
+                                               const double* B, int ldb,
+                                               double* C, int ldc,
+                                               double alpha, bool add) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  const int g = lane / 16, c16 = lane % 16;
+  const int TM = (m + 15) / 16, TN = (n + 15) / 16;
+  for (int t = wave; t < TM * TN; t += nw) {
+    const int m0 = (t % TM) * 16, n0 = (t / TM) * 16;
+    const int ra = m0 + c16, cb = n0 + c16;
+    const bool ina = ra < m, inb = cb < n;
+    const double* ap = A + (ina ? ra : 0);
+    const double* bp = B + (size_t)(inb ? cb : 0) * ldb;
+    auto lda_at = [&](int kk) {
+      return (ina && kk < k) ? ap[(size_t)kk * lda] : 0.0;
+    };
+    auto ldb_at = [&](int kk) { return (inb && kk < k) ? bp[kk] : 0.0; };
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+    // eight steps' operands are loaded together (an operand in global
+    // memory would otherwise cost its full latency per step)
+    for (int k0 = 0; k0 < k; k0 += 32) {
+      double a[8], b[8];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int r = rg + i * RG;
-      ap[i] = A + (r < m ? r : 0);
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      bp[j] = B + (size_t)(c0 + j < n ? c0 + j : 0) * ldb;
-    double acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-#pragma unroll 4
-    for (int kk = 0; kk < k; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        a[i] = *ap[i];
-        ap[i] += lda;
+      for (int q = 0; q < 8; ++q) {
+        a[q] = lda_at(k0 + 4 * q + g);
+        b[q] = ldb_at(k0 + 4 * q + g);
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = bp[j][kk];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+      for (int q = 0; q < 8; ++q)
+        if (k0 + 4 * q < k)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc, 0, 0, 0);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int r = rg + i * RG;
-        if (r < m && c0 + j < n) {
-          double* cp = C + (size_t)(c0 + j) * ldc + r;
-          *cp = (add ? *cp : 0.0) + alpha * acc[i][j];
-        }
+    for (int j = 0; j < 4; ++j) {
+      const int r = m0 + g + 4 * j;
+      if (r < m && inb) {
+        double* cp = C + (size_t)cb * ldc + r;
+        *cp = (add ? *cp : 0.0) + alpha * acc[j];
       }
+    }
   }
 }
-
 
 // Fused tail of one block (one workgroup).
 //  1. Combine the BCGS passes (Alg. 4): R(1:nb, k) = W + R2 Z and
@@ -454,10 +449,10 @@ __device__ __forceinline__ void tail_body(
   }
   __syncthreads();
   // 1. combine: Rt_top = W + R2 Z, Rkk = Zt Z
-  tile_gemm(nb, p, p, R2, nb, Z, p, Rt_top, nb, 1.0, true);
-  tile_gemm(p, p, p, Zt, p, Z, p, Rkk, p, 1.0, false);
+  tile_gemm_mfma(nb, p, p, R2, nb, Z, p, Rt_top, nb, 1.0, true);
+  tile_gemm_mfma(p, p, p, Zt, p, Z, p, Rkk, p, 1.0, false);
   // K = (Zi Zti)' into Tinv(1:p, 1:p)
-  if (p > 1) tile_gemm(p - 1, p - 1, p - 1, Zi, p, Zti, p, Tinv + p + 1, p,
+  if (p > 1) tile_gemm_mfma(p - 1, p - 1, p - 1, Zi, p, Zti, p, Tinv + p + 1, p,
                        1.0, false);
   __syncthreads();
   if (Rtop_out)
@@ -500,10 +495,10 @@ __device__ __forceinline__ void tail_body(
   }
   __syncthreads();
   if (nb > 1 && p > 1)
-    tile_gemm(nb, p - 1, i0, Hraw, ldh, Rt_top, nb, Mb + nr, nr, -1.0, true);
+    tile_gemm_mfma(nb, p - 1, i0, Hraw, ldh, Rt_top, nb, Mb + nr, nr, -1.0, true);
   __syncthreads();
   // Hn = M T^{-1}; write the new columns of H
-  tile_gemm(nr, p, p, Mb, nr, Tinv, p, Hn, nr, 1.0, false);
+  tile_gemm_mfma(nr, p, p, Mb, nr, Tinv, p, Hn, nr, 1.0, false);
   __syncthreads();
   for (int e = tid; e < nr * p; e += kSmallBlock) {
     const int r = e % nr, j = e / nr;
