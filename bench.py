@@ -104,9 +104,8 @@ def main():
                          "rocprof counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus "
-              f"{args.gpus} is not supported (the multi-GPU design is "
-              "described in DESIGN.md)", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU; --gpus "
+              f"{args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
