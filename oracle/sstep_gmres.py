@@ -19,6 +19,14 @@ numpy.linalg.svd (only for the optional exact condition number of Alg. 3).
 
 Readings of points the paper leaves open are marked "Reading:" and are
 listed in the design notes of the repository.
+
+Pins: the CPU tests check this module against facts outside itself (MGS
+GMRES, the GMRES minimiser by dense least squares, a dense LU solve,
+orthogonality and Arnoldi-relation bounds, the step sizes the paper prints
+for its Tests 1-3 and 8, closed forms, brute force on small inputs, finite
+differences), and planted mistakes must fail them.  Parity unpinned: the
+adapted step-size histories on the synthetic PDE workloads, for which the
+paper prints no values; the GPU path is compared with this module there.
 """
 from __future__ import annotations
 
