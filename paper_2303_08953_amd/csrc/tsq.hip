@@ -942,7 +942,26 @@ __global__ __launch_bounds__(kBlock) void k_col_dots(
 #pragma unroll
     for (int j = 0; j < CT; ++j)
       oc[j] = (int64_t)(c0 + j < ma ? c0 + j : 0) * Q.cstride;
-    for (int64_t pp = p0 + wave; pp < p1; pp += kBlock / kWave) {
+    // narrow tiles: two panels per iteration, all their loads issued
+    // together (wide tiles keep one: the registers would cost occupancy)
+    constexpr int NWV = kBlock / kWave;
+    int64_t pp = p0 + wave;
+    if (CT <= 4)
+    for (; pp + NWV < p1; pp += 2 * NWV) {
+      const T* ra = Q.base + Q.row_off(pp * kPanel) + lane;
+      const T* rc = Q.base + Q.row_off((pp + NWV) * kPanel) + lane;
+      const T va = ra[(int64_t)vcol * Q.cstride];
+      const T vc = rc[(int64_t)vcol * Q.cstride];
+      T qa[CT], qc[CT];
+#pragma unroll
+      for (int j = 0; j < CT; ++j) {
+        qa[j] = ra[oc[j]];
+        qc[j] = rc[oc[j]];
+      }
+#pragma unroll
+      for (int j = 0; j < CT; ++j) acc[j] += qa[j] * va + qc[j] * vc;
+    }
+    for (; pp < p1; pp += NWV) {
       const T* rb = Q.base + Q.row_off(pp * kPanel) + lane;
       const T v = rb[(int64_t)vcol * Q.cstride];
       T q[CT];
@@ -1432,11 +1451,27 @@ void col_dots(QView<const T> Q, int ma, int vcol, const int* pmask,
               hipStream_t st) {
   if (ma <= 0) return;
   const int64_t npanels = nrows / kPanel;
-  const int ctiles = (ma + kColTile - 1) / kColTile;
+  // column tile: 1, 4 or 8 columns for the first steps (no loads of
+  // absent columns), 16 beyond
+  const int ct = ma <= 1 ? 1 : (ma <= 4 ? 4 : (ma <= 8 ? 8 : kColTile));
+  const int ctiles = (ma + ct - 1) / ct;
   const int chunks = col_chunks(npanels, ctiles, ma, P);
-  hipLaunchKernelGGL((k_col_dots<T, kColTile>), dim3(chunks * ctiles),
-                     dim3(kBlock), 0, st, Q, ma, vcol, pmask, npanels, ctiles,
-                     chunks, P.buf);
+  if (ct == 1)
+    hipLaunchKernelGGL((k_col_dots<T, 1>), dim3(chunks * ctiles),
+                       dim3(kBlock), 0, st, Q, ma, vcol, pmask, npanels,
+                       ctiles, chunks, P.buf);
+  else if (ct == 4)
+    hipLaunchKernelGGL((k_col_dots<T, 4>), dim3(chunks * ctiles),
+                       dim3(kBlock), 0, st, Q, ma, vcol, pmask, npanels,
+                       ctiles, chunks, P.buf);
+  else if (ct == 8)
+    hipLaunchKernelGGL((k_col_dots<T, 8>), dim3(chunks * ctiles),
+                       dim3(kBlock), 0, st, Q, ma, vcol, pmask, npanels,
+                       ctiles, chunks, P.buf);
+  else
+    hipLaunchKernelGGL((k_col_dots<T, kColTile>), dim3(chunks * ctiles),
+                       dim3(kBlock), 0, st, Q, ma, vcol, pmask, npanels,
+                       ctiles, chunks, P.buf);
   SGM_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(kRedWaves * kWave), 0, st,
                      (const double*)P.buf, (int64_t)chunks, ma, 0, pmask,
