@@ -128,6 +128,7 @@ struct HostMirror {
 constexpr size_t kSlotCtrlOff = 32 * 1024;  // kMaxSlots x kSlotInts ints
 constexpr int kSlotInts = 8;
 constexpr int kMaxSlots = 256;
+constexpr int kStepBatch = 32;  // column-wise steps queued per synchronisation
 constexpr size_t kSlotResOff =
     kSlotCtrlOff + sizeof(int) * kSlotInts * kMaxSlots;  // kMaxSlots doubles
 static_assert(C_NCTRL <= kSlotInts, "control words do not fit a slot");
@@ -413,18 +414,19 @@ struct Engine {
     return b;
   }
 
-  // The column-wise pre-phase steps 1..nsteps (s = 1, monomial), queued
-  // back to back with one host synchronisation at the end: every step's
+  // The column-wise pre-phase steps t0 + 1 .. t0 + nsteps (s = 1,
+  // monomial), queued back to back with one host synchronisation at the
+  // end (the stop word is cleared with the first batch): every step's
   // tail writes its control words and estimate into its own slot of the
   // mapped host memory, and the tail that ends the cycle (convergence,
   // breakdown, non-finite estimate) sets the device stop word, after which
   // the queued tails leave the Hessenberg and Givens state untouched (the
   // other kernels of those steps only touch columns the cycle no longer
   // uses).  Returns the slots' control words in order.
-  std::vector<BlockOut> column_steps(int nsteps, const double* beta0,
+  std::vector<BlockOut> column_steps(int t0, int nsteps, const double* beta0,
                                      double tol) {
-    SGM_HIP(hipMemsetAsync(w.ctrl + C_STOP, 0, sizeof(int), st));
-    for (int t = 0; t < nsteps; ++t) {
+    if (t0 == 0) SGM_HIP(hipMemsetAsync(w.ctrl + C_STOP, 0, sizeof(int), st));
+    for (int t = t0; t < t0 + nsteps; ++t) {
       const int nbt = 1 + t;
       spmv_mpk<T>(S, vals, Q(), nbt - 1, -1, nbt, w.mono, 0, st);
       orth_block<T>(Q(), ld, nbt, 1, omega, w, st, false);
@@ -436,7 +438,7 @@ struct Engine {
     }
     wait_stream(st);
     std::vector<BlockOut> out;
-    for (int t = 0; t < nsteps; ++t) {
+    for (int t = t0; t < t0 + nsteps; ++t) {
       const int* c = hm.slot_ctrl + (size_t)kSlotInts * t;
       BlockOut b;
       b.p2 = c[C_P2];
@@ -470,26 +472,33 @@ struct Engine {
     auto t_pre = Clock::now();
     bool timing_pre = !sh.known;
     if (!sh.known && s_pre == 1 && m0 >= 1 && m0 <= kMaxSlots) {
-      // the column-wise pre-phase, queued without per-step synchronisation
-      const std::vector<BlockOut> bs =
-          column_steps(m0, beta0_dev, prephase_only ? -1.0 : tol);
-      for (size_t t = 0; t < bs.size(); ++t) {
-        const BlockOut& b = bs[t];
-        if (b.bad) throw Error{SGM_ENUMERIC, "non-finite residual estimate"};
-        if (!prephase_only) {
-          // one column per step: kdone is 0 or 1
-          if (b.kdone > 0) res.res_hist.push_back(hm.slot_res[t] * res_scale);
-          res.s_hist.push_back(b.brk ? 0 : b.p2);
-          if (b.kdone > 0) res.rel_est = hm.slot_res[t] * res_scale;
+      // the column-wise pre-phase, queued in batches without per-step
+      // synchronisation (a batch bounds the steps queued past the end of
+      // a cycle that converges early)
+      for (int t0 = 0; t0 < m0 && !conv; t0 += kStepBatch) {
+        const int cnt = std::min(kStepBatch, m0 - t0);
+        const std::vector<BlockOut> bs =
+            column_steps(t0, cnt, beta0_dev, prephase_only ? -1.0 : tol);
+        for (size_t u = 0; u < bs.size(); ++u) {
+          const BlockOut& b = bs[u];
+          const size_t t = t0 + u;
+          if (b.bad) throw Error{SGM_ENUMERIC, "non-finite residual estimate"};
+          if (!prephase_only) {
+            // one column per step: kdone is 0 or 1
+            if (b.kdone > 0)
+              res.res_hist.push_back(hm.slot_res[t] * res_scale);
+            res.s_hist.push_back(b.brk ? 0 : b.p2);
+            if (b.kdone > 0) res.rel_est = hm.slot_res[t] * res_scale;
+          }
+          k = nb - 1 + b.kdone;
+          if (b.brk) {
+            conv = true;
+            break;
+          }
+          if (b.conv) conv = true;
+          nb += b.p2;
+          if (conv) break;
         }
-        k = nb - 1 + b.kdone;
-        if (b.brk) {
-          conv = true;
-          break;
-        }
-        if (b.conv) conv = true;
-        nb += b.p2;
-        if (conv) break;
       }
     }
     while (nb <= last && !conv) {

@@ -129,3 +129,29 @@ def test_invalid_options_rejected(lib, bad):
     with pytest.raises(lib.SgmError) as e:
         gpu_solve(lib, A, b, **kw)
     assert e.value.status == lib.EINVAL
+
+
+@pytest.mark.parametrize("shift", [2.5, 3.0])
+def test_converges_inside_queued_prephase(lib, shift):
+    """s_max 100: the column-wise pre-phase (100 steps) is queued in batches
+    of 32 without per-step synchronisation, and the solve converges inside
+    it (42 or 62 iterations, the second batch).  Iterations, residual
+    history and solution match the oracle; the steps queued past
+    convergence change nothing."""
+    rng = np.random.default_rng(7)
+    n = 3000
+    A = sp.random(n, n, density=0.003, random_state=rng, format="csr")
+    A = (A + sp.eye(n) * shift).tocsr()
+    b = rng.standard_normal(n)
+    kw = dict(s_max=100, restart=128, tol=1e-10, max_restarts=5)
+    ref = o.solve(A, b, opts=o.Options(**kw))
+    r = gpu_solve(lib, A, b, **kw)
+    assert r.status == lib.OK and ref.status == "ok"
+    assert 32 < ref.iters <= 64
+    assert r.info["iters"] == ref.iters
+    assert list(r.s_hist) == ref.s_hist
+    h, hr = np.array(r.res_hist), np.array(ref.res_hist)
+    assert np.all(np.abs(h - hr) <= 1e-6 * hr)
+    x = r.x.cpu().numpy()
+    assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+    assert np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b)
