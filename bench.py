@@ -16,7 +16,9 @@ with its speedup over the float64 default.  Prints ONE JSON line (see keys
 below).
 
 Roofline: the dominant kernel is the SELL SpMV of the matrix powers kernel
-(float64).  Its average launch duration comes from the HIP event pair the
+(float64); its rate is also given against a measured triad bandwidth
+(torch's a = b + alpha c on three 1 GiB float64 vectors) and, when the
+counters are current, on its measured bytes.  Its average launch duration comes from the HIP event pair the
 library records around every MPK launch on the solve's stream, during the
 timed steps; algorithmic bytes per launch are
 nnz (8 + 4) + 4 (n + 1) + 2 * 8 n (values + column indices, row pointers,
@@ -65,6 +67,30 @@ def load_traffic(kernel_hash):
     if d.get("spmv_source_sha256_16") != kernel_hash:
         return None
     return d.get("hbm_bytes_per_launch")
+
+
+def measure_triad(torch, nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth for a triad a = b + alpha c (torch's own
+    elementwise kernel, float64, three 1 GiB vectors, cold in the 256 MB
+    Infinity Cache): GB/s counting 2 reads and 1 write per element."""
+    n = nbytes // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    c = torch.rand(n, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        torch.add(b, c, alpha=0.5, out=a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.add(b, c, alpha=0.5, out=a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b, c
+    torch.cuda.empty_cache()
+    return 3 * n * 8 / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(A, b, gpu_iters, restart, s_max):
@@ -230,13 +256,19 @@ def main():
     alg_bytes = A.nnz * (vb + 4) + 4 * (A.n + 1) + 2 * vb * A.n
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     khash = spmv_source_hash()
+    traffic = load_traffic(khash)
+    triad = measure_triad(torch)
     out["roofline"] = {
         "kernel": f"k_spmv<{'double' if vb == 8 else 'float'}, EPI_MPK, "
                   "int16_t> (SELL-C-64 SpMV of the matrix powers kernel, "
                   "16-bit column deltas; achieved is on the CSR bytes)",
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-        "traffic": load_traffic(khash),
+        "traffic": traffic,
+        "measured_triad_gbs": round(triad, 1),
+        "frac_of_triad": round(achieved / triad, 4),
+        "traffic_gbs": (round(traffic / (avg_ms * 1e-3) / 1e9, 1)
+                        if traffic else None),
         "algorithmic_bytes_per_launch": int(alg_bytes),
         "avg_launch_us": round(avg_ms * 1e3, 2), "launches": int(n_spmv),
         "spmv_source_sha256_16": khash}
