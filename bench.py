@@ -29,6 +29,19 @@ current SpMV source (matching hash), else null.
 CPU baseline: the oracle (numpy/scipy, float64) timed on the host on a
 bounded sample -- one full restart cycle (128 iterations) of the same solve
 -- and scaled to the float64 solve's iteration count.
+
+--workload selects one of the other synthetic workloads instead (same JSON
+line; no CPU baseline, whose bounded sample would not fit in minutes):
+  varcd3d_192   3D variable-coefficient convection-diffusion 192^3 (n =
+                7.1M) with right Jacobi, s_max 128, restart 256: float64
+                and float32-IR to 1e-10, column-wise and monomial pre-phase;
+  aniso2d_4096  2D anisotropic diffusion 4096^2 (n = 16.8M), s_max 200,
+                restart 400, no preconditioner (condition ~1e7): float64 and
+                float32-IR with capped restarts (it does not reach 1e-10 in
+                minutes), plus the backward solve for the gradient w.r.t. b;
+  banded_1m     random banded nonsymmetric n = 1M, 27 nonzeros per row:
+                the differentiable solve to 1e-12, forward and backward
+                (adjoint solve + gradient w.r.t. the CSR values).
 """
 from __future__ import annotations
 
@@ -116,12 +129,237 @@ def cpu_baseline(A, b, gpu_iters, restart, s_max):
                        f"GPU solve's {gpu_iters} iterations")}
 
 
+def solve_summary(sgm, rs, ms_list, tol):
+    """Per-mode figures of a list of SolveResults and their wall times."""
+    import numpy as np
+    last = rs[-1]
+    i = last.info
+    ok = all(r.status == sgm.OK and r.info["rel_res_true"] <= tol for r in rs)
+    ph = i["t_phase_ms"]
+    return {"ms": round(float(np.mean(ms_list)), 3),
+            "ms_min": round(float(np.min(ms_list)), 3),
+            "converged": bool(ok), "iters": i["iters"],
+            "restarts": i["restarts"], "outer_iters": i["outer_iters"],
+            "rel_res_true": i["rel_res_true"], "s0_est": i["s0_est"],
+            "s_init": i["s_init"], "blocks": int(len(last.s_hist)),
+            "ms_per_iter": round(float(np.mean(ms_list)) / max(1, i["iters"]),
+                                 4),
+            "s_hist_head": [int(v) for v in last.s_hist[:24]],
+            "phase_ms": {"setup": round(ph[0], 3),
+                         "prephase_shifts": round(ph[1], 3),
+                         "mpk": round(ph[2], 3), "orth": round(ph[3], 3),
+                         "hess_givens": round(ph[4], 3),
+                         "cycle_end": round(ph[5], 3),
+                         "total": round(ph[7], 3)},
+            "spmv_avg_us": round(i["t_spmv_ms"] / max(1, i["n_spmv"]) * 1e3,
+                                 2)}
+
+
+def spmv_roofline(A, G, rs, vb, label):
+    """Rate of the matrix powers SpMV over the solves rs: CSR algorithmic
+    bytes nnz (vb + 4) + 4 (n + 1) + 2 vb n per launch over the average
+    launch time (HIP events around every MPK launch); also the SELL
+    format's own minimum, padded entries times (vb + index bytes) plus
+    x and y."""
+    info = G.info()
+    n_spmv = sum(r.info["n_spmv"] for r in rs)
+    t_spmv = sum(r.info["t_spmv_ms"] for r in rs)
+    avg_ms = t_spmv / max(1, n_spmv)
+    alg = A.nnz * (vb + 4) + 4 * (A.n + 1) + 2 * vb * A.n
+    fmt = info["sell_nnz"] * (vb + info["index_bytes"]) + 2 * vb * A.n
+    ach = alg / (avg_ms * 1e-3) / 1e9
+    return {"kernel": f"k_spmv<{label}, EPI_MPK, "
+                      f"{'int16_t' if info['index_bytes'] == 2 else 'int32_t'}>"
+                      " (SELL-C-64 SpMV of the matrix powers kernel; "
+                      "achieved is on the CSR bytes)",
+            "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": None, "algorithmic_bytes_per_launch": int(alg),
+            "format_bytes_per_launch": int(fmt),
+            "format_gbs": round(fmt / (avg_ms * 1e-3) / 1e9, 1),
+            "index_bytes": info["index_bytes"],
+            "avg_launch_us": round(avg_ms * 1e3, 2), "launches": int(n_spmv)}
+
+
+def study(args, np, torch, sgm, W):
+    """One JSON line for a workload other than the default (see the module
+    docstring): every mode is warmed up once with its restarts capped at
+    one cycle (kernels loaded, workspace allocated), then timed."""
+    name = args.workload
+    log(f"[bench] building {name}")
+    if name == "banded_1m":
+        return study_adjoint(args, np, torch, sgm, W)
+    if name == "varcd3d_192":
+        A = W.var_conv_diff_3d(192, 3)
+        b_host = W.rhs(A.n, 3)
+        base = dict(s_max=128, restart=256, tol=1e-10, precond="jacobi",
+                    max_restarts=200)
+        b32 = dict(base, precision="fp32_ir", inner_tol=1e-6, max_outer=100)
+        modes = [("fp64", base), ("fp32_ir", b32),
+                 ("fp64_monomial_prephase", dict(base, prephase="monomial")),
+                 ("fp32_ir_monomial_prephase",
+                  dict(b32, prephase="monomial"))]
+        cfg = {"workload": name,
+               "matrix": "3D variable-coefficient convection-diffusion "
+                         "7-point 192^3, lognormal(0,1) cells, harmonic faces,"
+                         " velocity (20,10,5) upwind, Dirichlet",
+               "precond": "jacobi (right)", "s_max": 128, "restart": 256,
+               "rhs": "N(0,1) seed 3"}
+    else:  # aniso2d_4096
+        A = W.aniso_diffusion_2d(4096)
+        b_host = W.rhs(A.n, 5)
+        base = dict(s_max=200, restart=400, tol=1e-10, max_restarts=4)
+        b32 = dict(base, precision="fp32_ir", inner_tol=1e-6, max_outer=5,
+                   max_restarts=1000)
+        modes = [("fp64", base), ("fp32_ir", b32),
+                 ("fp64_monomial_prephase", dict(base, prephase="monomial")),
+                 ("fp32_ir_monomial_prephase",
+                  dict(b32, prephase="monomial")),
+                 ("fp32_ir_monomial_no_estimator",
+                  dict(b32, prephase="monomial", use_estimator=False))]
+        cfg = {"workload": name,
+               "matrix": "2D anisotropic diffusion 5-point 4096^2, "
+                         "K = R(30deg) diag(1, 1e-3) R^T, K_xy dropped",
+               "precond": "none", "s_max": 200, "restart": 400,
+               "caps": "float64: 5 restart cycles; float32-IR: 5 outer steps",
+               "rhs": "N(0,1) seed 5"}
+    cfg.update({"n": A.n, "nnz": A.nnz, "basis": "scaled_newton",
+                "tol": 1e-10, "x0": "zero"})
+    G = sgm.Matrix.from_csr(A)
+    b = torch.tensor(b_host, device="cuda")
+    x = torch.empty_like(b)
+    ws = sgm.Workspace()
+    for mname, o in modes:
+        cap = dict(o, max_restarts=0, max_outer=1)
+        t0 = time.perf_counter()
+        sgm.solve(G, b, out=x, workspace=ws, **cap)
+        torch.cuda.synchronize()
+        log(f"[bench] warmup {mname}: {(time.perf_counter() - t0) * 1e3:.0f}"
+            " ms")
+    per, infos = {}, {}
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        for mname, o in modes:
+            t0 = time.perf_counter()
+            r = sgm.solve(G, b, out=x, workspace=ws, **o)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            per.setdefault(mname, []).append(ms)
+            infos.setdefault(mname, []).append(r)
+            log(f"[bench] step {k} {mname}: {ms:.1f} ms iters "
+                f"{r.info['iters']} rel {r.info['rel_res_true']:.2e}")
+    total_ms = (time.perf_counter() - t_start) * 1e3
+    out = {"metric": METRIC, "unit": "ms", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1,
+           "ms_per_step": round(total_ms / max(1, args.steps), 3),
+           "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic",
+           "value": round(float(np.mean(per["fp64"])), 3), "dtype": "f64",
+           "config": cfg}
+    for mname, _ in modes:
+        out[mname] = solve_summary(sgm, infos[mname], per[mname], 1e-10)
+        if mname != "fp64":
+            out[mname]["speedup_vs_fp64"] = round(
+                out["fp64"]["ms"] / out[mname]["ms"], 3)
+    out["roofline"] = spmv_roofline(A, G, infos["fp64"], 8, "double")
+    out["roofline_fp32"] = spmv_roofline(A, G, infos["fp32_ir"], 4, "float")
+    if name == "aniso2d_4096":
+        # backward solve for the gradient w.r.t. b (float32-IR, same caps)
+        bt = torch.tensor(b_host, device="cuda", requires_grad=True)
+        vals = torch.tensor(A.val, device="cuda")
+        o = dict(b32, prephase="monomial")
+        t0 = time.perf_counter()
+        xg = sgm.sstep_solve(vals, bt, G, **o)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        (0.5 * (xg ** 2).sum()).backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out["fp32_ir_with_backward"] = {
+            "forward_ms": round((t1 - t0) * 1e3, 1),
+            "backward_ms": round((t2 - t1) * 1e3, 1),
+            "grad_b_finite": bool(torch.isfinite(bt.grad).all().item())}
+    out["cpu_baseline"] = None
+    return out
+
+
+def study_adjoint(args, np, torch, sgm, W):
+    """banded_1m: the differentiable solve x = A(vals)^{-1} b to 1e-12 and
+    the backward pass of L = 0.5 ||x - x*||^2 (adjoint solve on A^T and the
+    gradient w.r.t. the CSR values), timed together; the plain forward and
+    transposed solves are timed alone for their iteration counts."""
+    A, b_host, xs_host = W.banded_problem(1_000_000, seed=4, band=1000)
+    G = sgm.Matrix.from_csr(A)
+    opts = dict(s_max=32, restart=128, tol=1e-12, max_restarts=200)
+    vals = torch.tensor(A.val, device="cuda", requires_grad=True)
+    bt = torch.tensor(b_host, device="cuda", requires_grad=True)
+    xs = torch.tensor(xs_host, device="cuda")
+    ws = sgm.Workspace()
+
+    def diff_step():
+        vals.grad = None
+        bt.grad = None
+        t0 = time.perf_counter()
+        x = sgm.sstep_solve(vals, bt, G, **opts)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        (0.5 * ((x - xs) ** 2).sum()).backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return (t1 - t0) * 1e3, (t2 - t1) * 1e3
+
+    f, bw = diff_step()
+    log(f"[bench] warmup: forward {f:.1f} ms backward {bw:.1f} ms")
+    fw, bk, tot = [], [], []
+    for k in range(args.steps):
+        f, bw = diff_step()
+        fw.append(f)
+        bk.append(bw)
+        tot.append(f + bw)
+        log(f"[bench] step {k}: forward {f:.1f} ms backward {bw:.1f} ms")
+    plain = {}
+    for mname, o in (("forward_solve", opts),
+                     ("adjoint_solve", dict(opts, transpose=True))):
+        t0 = time.perf_counter()
+        r = sgm.solve(G, torch.tensor(b_host, device="cuda"), workspace=ws,
+                      **o)
+        torch.cuda.synchronize()
+        plain[mname] = solve_summary(sgm, [r],
+                                     [(time.perf_counter() - t0) * 1e3],
+                                     1e-12)
+        plain[mname]["_r"] = r
+    out = {"metric": METRIC, "unit": "ms", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1,
+           "ms_per_step": round(float(np.mean(tot)), 3),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "data": "synthetic", "value": round(float(np.mean(tot)), 3),
+           "dtype": "f64",
+           "config": {"workload": "banded_1m",
+                      "matrix": "random banded nonsymmetric, 26 off-diagonals"
+                                " U(-1,1) within |i-j| <= 1000, diagonal "
+                                "1.2 x row abs sum",
+                      "n": A.n, "nnz": A.nnz, "s_max": 32, "restart": 128,
+                      "tol": 1e-12, "loss": "0.5 ||x - x*||^2",
+                      "rhs": "N(0,1) seed 1004, x* N(0,1)"},
+           "differentiable_step": {"forward_ms": round(float(np.mean(fw)), 3),
+                                   "backward_ms": round(float(np.mean(bk)),
+                                                        3)}}
+    rs = {k: plain[k].pop("_r") for k in plain}
+    out.update(plain)
+    out["roofline"] = spmv_roofline(A, G, [rs["forward_solve"]], 8, "double")
+    out["cpu_baseline"] = None
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nx", type=int, default=128)
+    ap.add_argument("--workload", default="poisson3d_128",
+                    choices=["poisson3d_128", "varcd3d_192", "aniso2d_4096",
+                             "banded_1m"])
     ap.add_argument("--mode", choices=["both", "fp64", "fp32_ir", "all"],
                     default="all")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -141,6 +379,9 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.workload != "poisson3d_128":
+        print(json.dumps(study(args, np, torch, sgm, W)), flush=True)
+        return
     s_max, restart, tol = 32, 128, 1e-10
     log(f"[bench] building poisson3d_{args.nx}")
     A = W.poisson_3d(args.nx)

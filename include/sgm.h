@@ -95,9 +95,13 @@ sgm_status sgm_matrix_update_values(sgm_matrix A, const double* val,
 
 sgm_status sgm_matrix_destroy(sgm_matrix A);
 
-/* n and nnz of an analysed matrix (host outputs, may be NULL). */
+/* Sizes of an analysed matrix (host outputs, each may be NULL): n, nnz,
+ * the padded SELL-C-64 entry count of A, and index_bytes[2] = the bytes
+ * per column index the SpMV of A and of A^T reads: 2 when every group of 64
+ * entries (one slice position) has its columns within 65535 of each other
+ * after removing the lane offset (stencils, banded matrices), else 4. */
 sgm_status sgm_matrix_info(sgm_matrix A, int64_t* n, int64_t* nnz,
-                           int64_t* sell_nnz);
+                           int64_t* sell_nnz, int32_t* index_bytes);
 
 /* y = A x (transpose = 0) or y = A^T x (transpose = 1).
  * precision SGM_FP64: x, y are double[n]; SGM_FP32_IR: float[n] with the

@@ -78,7 +78,8 @@ _SIGS = [
     ("sgm_matrix_update_values", C.c_int, [_P, _P, _P]),
     ("sgm_matrix_destroy", C.c_int, [_P]),
     ("sgm_matrix_info", C.c_int,
-     [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+     [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+      C.POINTER(C.c_int32)]),
     ("sgm_spmv", C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P]),
     ("sgm_opts_default", None, [C.POINTER(Opts)]),
     ("sgm_workspace_size", C.c_int, [_P, C.POINTER(Opts), C.POINTER(C.c_size_t)]),
@@ -188,9 +189,11 @@ class Matrix:
 
     def info(self):
         n, nnz, snnz = C.c_int64(), C.c_int64(), C.c_int64()
+        ib = (C.c_int32 * 2)()
         _check(lib().sgm_matrix_info(self._h, C.byref(n), C.byref(nnz),
-                                     C.byref(snnz)))
-        return dict(n=n.value, nnz=nnz.value, sell_nnz=snnz.value)
+                                     C.byref(snnz), ib))
+        return dict(n=n.value, nnz=nnz.value, sell_nnz=snnz.value,
+                    index_bytes=ib[0], index_bytes_t=ib[1])
 
     def spmv(self, x, transpose=False, precision="fp64", out=None,
              stream=None):

@@ -104,6 +104,8 @@ inline QView<T> colmajor_view(T* base, int64_t ld) {
 // Slice s covers rows [64 s, 64 s + 64); its entries sit at
 // ptr[s] + w * 64 + lane for w < width[s]; padding has val 0 and a column
 // index that is already being read by the same lane (no extra traffic).
+// Every ptr[s] is a multiple of 64, so ptr[s] / 64 + w numbers the
+// (slice, position) groups of 64 entries.
 struct Sell {
   int64_t n = 0;
   int64_t nslices = 0;
@@ -111,10 +113,14 @@ struct Sell {
   int64_t* ptr = nullptr;   // [nslices + 1]
   int32_t* width = nullptr; // [nslices]
   int32_t* col = nullptr;   // [nnz_padded]
-  // [nnz_padded] col - row as 16 bits, present when every entry's distance
-  // from the diagonal fits (then the SpMV reads these 2-byte deltas
-  // instead of the 4-byte columns); rows past n point at row n - 1
-  int16_t* dcol = nullptr;
+  // 16-bit relative columns, present when they fit (then the SpMV reads
+  // these 2-byte offsets instead of the 4-byte columns): the entry of lane l
+  // in group g = ptr[s] / 64 + w has column kbase[g] + l + rcol[entry].
+  // kbase[g] is the midpoint of (column - lane) over the group's real rows,
+  // so a group fits when that range spans at most 65535 (stencils of any
+  // grid size, banded matrices); rows past n decode to a valid column.
+  int16_t* rcol = nullptr;  // [nnz_padded]
+  int32_t* kbase = nullptr; // [nnz_padded / 64]
   int64_t* src = nullptr;   // [nnz_padded] CSR index of each entry, -1 = pad
   double* val64 = nullptr;  // [nnz_padded]
   float* val32 = nullptr;   // [nnz_padded]

@@ -88,40 +88,53 @@ __global__ void k_sell_fill(const int32_t* rp, const int32_t* col,
   }
 }
 
-// Largest |col - row| over the real rows of a SELL matrix (integer max:
-// the result does not depend on the order of the atomics).
-__global__ void k_sell_max_delta(const int32_t* scol, const int64_t* ptr,
-                                 const int32_t* width, int64_t n,
-                                 int64_t nslices, int32_t* out) {
+// Group bases of the 16-bit relative columns.  One wavefront per slice;
+// for every position w < width[s], the group's (column - lane) values over
+// the slice's real rows (lane 0 always is one) give lo and hi; the base is
+// lo + ceil((hi - lo) / 2), so every offset lies in [-32768, 32767] exactly
+// when hi - lo <= 65535.  out[0] = the largest hi - lo (integer max: the
+// result does not depend on the order of the atomics).
+__global__ void k_sell_bases(const int32_t* scol, const int64_t* ptr,
+                             const int32_t* width, int64_t n, int64_t nslices,
+                             int32_t* kbase, int32_t* out) {
   int64_t s = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave;
   int lane = threadIdx.x % kWave;
   if (s >= nslices) return;
-  int64_t r = s * kSlice + lane;
-  int64_t base = ptr[s] + lane;
-  int w = width[s];
-  int32_t m = 0;
-  if (r < n)
-    for (int k = 0; k < w; ++k) {
-      const int64_t d = (int64_t)scol[base + (int64_t)k * kSlice] - r;
-      const int64_t a = d < 0 ? -d : d;
-      m = max(m, (int32_t)min(a, (int64_t)INT32_MAX));
+  const int64_t r = s * kSlice + lane;
+  const int64_t base = ptr[s] + lane;
+  const int w = width[s];
+  int64_t span = 0;
+  for (int k = 0; k < w; ++k) {
+    const int64_t v = (int64_t)scol[base + (int64_t)k * kSlice] - lane;
+    int64_t lo = r < n ? v : INT64_MAX, hi = r < n ? v : INT64_MIN;
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      lo = min(lo, (int64_t)__shfl_xor((long long)lo, off));
+      hi = max(hi, (int64_t)__shfl_xor((long long)hi, off));
     }
-  for (int off = kWave / 2; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
-  if (lane == 0) atomicMax(out, m);
+    if (lane == 0) kbase[(ptr[s] >> 6) + k] = (int32_t)(lo + (hi - lo + 1) / 2);
+    span = max(span, hi - lo);
+  }
+  if (lane == 0) atomicMax(out, (int32_t)min(span, (int64_t)INT32_MAX));
 }
 
-__global__ void k_sell_deltas(const int32_t* scol, const int64_t* ptr,
-                              const int32_t* width, int64_t n, int64_t nslices,
-                              int16_t* dcol) {
+// 16-bit offsets against the group bases; rows past n take the column
+// base + lane clamped to [0, n) (value 0, a valid gather address).
+__global__ void k_sell_rel16(const int32_t* scol, const int64_t* ptr,
+                             const int32_t* width, const int32_t* kbase,
+                             int64_t n, int64_t nslices, int16_t* rcol) {
   int64_t s = blockIdx.x * (int64_t)(blockDim.x / kWave) + threadIdx.x / kWave;
   int lane = threadIdx.x % kWave;
   if (s >= nslices) return;
-  int64_t r = s * kSlice + lane;
-  int64_t base = ptr[s] + lane;
-  int w = width[s];
+  const int64_t r = s * kSlice + lane;
+  const int64_t base = ptr[s] + lane;
+  const int w = width[s];
   for (int k = 0; k < w; ++k) {
     const int64_t e = base + (int64_t)k * kSlice;
-    dcol[e] = (int16_t)(r < n ? (int64_t)scol[e] - r : (n - 1) - r);
+    const int64_t b = kbase[(ptr[s] >> 6) + k];
+    int64_t c = b + lane;
+    if (r < n) c = scol[e];
+    else c = c < 0 ? 0 : (c > n - 1 ? n - 1 : c);
+    rcol[e] = (int16_t)(c - lane - b);
   }
 }
 
@@ -210,25 +223,27 @@ void sell_build(Sell& S, int64_t n, const int32_t* rp, const int32_t* col,
                      dim3(wpb * kWave), 0, st, rp, col, perm, n, S.nslices,
                      S.ptr, S.width, S.col, S.src);
   SGM_CHECK_LAUNCH();
-  // 16-bit column deltas when every entry lies within 32767 of the
-  // diagonal (stencils, banded matrices)
-  int32_t* dmax = dmalloc<int32_t>(1);
-  SGM_HIP(hipMemsetAsync(dmax, 0, sizeof(int32_t), st));
-  hipLaunchKernelGGL(k_sell_max_delta, dim3(grid1(S.nslices, wpb)),
+  // 16-bit relative columns when every group's column range fits
+  S.kbase = dmalloc<int32_t>(total / kSlice);
+  int32_t* dspan = dmalloc<int32_t>(1);
+  SGM_HIP(hipMemsetAsync(dspan, 0, sizeof(int32_t), st));
+  hipLaunchKernelGGL(k_sell_bases, dim3(grid1(S.nslices, wpb)),
                      dim3(wpb * kWave), 0, st, S.col, S.ptr, S.width, n,
-                     S.nslices, dmax);
+                     S.nslices, S.kbase, dspan);
   SGM_CHECK_LAUNCH();
-  int32_t hmax = 0;
-  SGM_HIP(hipMemcpyAsync(&hmax, dmax, sizeof(int32_t), hipMemcpyDeviceToHost,
-                         st));
+  int32_t hspan = 0;
+  SGM_HIP(hipMemcpyAsync(&hspan, dspan, sizeof(int32_t),
+                         hipMemcpyDeviceToHost, st));
   SGM_HIP(hipStreamSynchronize(st));
-  dfree(dmax);
-  if (hmax <= 32767 && n >= 1) {
-    S.dcol = dmalloc<int16_t>(total);
-    hipLaunchKernelGGL(k_sell_deltas, dim3(grid1(S.nslices, wpb)),
-                       dim3(wpb * kWave), 0, st, S.col, S.ptr, S.width, n,
-                       S.nslices, S.dcol);
+  dfree(dspan);
+  if (hspan <= 65535 && n >= 1) {
+    S.rcol = dmalloc<int16_t>(total);
+    hipLaunchKernelGGL(k_sell_rel16, dim3(grid1(S.nslices, wpb)),
+                       dim3(wpb * kWave), 0, st, S.col, S.ptr, S.width,
+                       S.kbase, n, S.nslices, S.rcol);
     SGM_CHECK_LAUNCH();
+  } else {
+    dfree(S.kbase);
   }
 }
 
@@ -242,7 +257,8 @@ void sell_free(Sell& S) {
   dfree(S.ptr);
   dfree(S.width);
   dfree(S.col);
-  dfree(S.dcol);
+  dfree(S.rcol);
+  dfree(S.kbase);
   dfree(S.src);
   dfree(S.val64);
   dfree(S.val32);

@@ -51,8 +51,24 @@ struct Work {
   int* ctrl = nullptr;     // C_NCTRL
   int* info = nullptr;     // 0 hqr status, 1..3 leja info
   int64_t ld = 0;
+  int qcols = 0;  // columns of the basis panels (>= m + 2)
   int ldw = 0, lds = 0, ldh = 0;
 };
+
+// Columns of the basis panels: at least m + 2, skipping counts whose panel
+// stride (64 rows x columns x value bytes) lies within 2 KiB of a multiple
+// of 64 KiB.  Measured on the matrix powers SpMV, whose x gathers and y
+// stores hop from panel to panel: such strides (128 or 254-258 float64
+// columns, 254-258 or 512 float32 columns) slow it by 15-50%, on 2D and 3D
+// stencils alike; the strides around them run at full speed.
+int basis_cols(int m, int vb) {
+  int c = m + 2;
+  for (;;) {
+    const int64_t rem = (int64_t)kPanel * c * vb % 65536;
+    if ((rem < 65536 - rem ? rem : 65536 - rem) >= 2048) return c;
+    ++c;
+  }
+}
 
 int64_t part_cap(int m, int smax) {
   int64_t a = (int64_t)1 << 22;
@@ -66,10 +82,11 @@ void layout(Arena& a, Work& w, int64_t n, int64_t sell_nnz, int m, int smax,
   w.ldw = m + 1;
   w.lds = smax;
   w.ldh = m + 1;
+  w.qcols = basis_cols(m, fp32 ? 4 : 8);
   if (fp32)
-    w.Q = a.take<float>(w.ld * (m + 2));
+    w.Q = a.take<float>(w.ld * w.qcols);
   else
-    w.Q = a.take<double>(w.ld * (m + 2));
+    w.Q = a.take<double>(w.ld * w.qcols);
   w.r = a.take<double>(w.ld);
   if (jacobi) {
     w.jac64 = a.take<double>(sell_nnz);
@@ -298,8 +315,8 @@ struct Engine {
     for (auto& e : ev) (void)hipEventDestroy(e);
   }
 
-  // the basis Q(:, 0 : m+1) in 64-row panels
-  QView<T> Q() const { return panel_view<T>(static_cast<T*>(w.Q), m + 2); }
+  // the basis Q(:, 0 : m+1) in 64-row panels of w.qcols columns
+  QView<T> Q() const { return panel_view<T>(static_cast<T*>(w.Q), w.qcols); }
 
   void set_monomial() {
     const double mono[3] = {0.0, 1.0, 0.0};
@@ -582,8 +599,8 @@ void run_solve(Handle* h, const double* b, const double* x0, double* x,
     SGM_HIP(hipMemcpyAsync(x, x0, sizeof(double) * n, hipMemcpyDeviceToDevice,
                            st));
   if (jac) vec_scale_div(x, A.diag, n, false, st);
-  zero_pad_rows<T>(panel_view<T>(static_cast<T*>(w.Q), o.restart + 2), n,
-                   w.ld, o.restart + 2, st);
+  zero_pad_rows<T>(panel_view<T>(static_cast<T*>(w.Q), w.qcols), n, w.ld,
+                   o.restart + 2, st);
   const double one = 1.0;
   SGM_HIP(hipMemcpyAsync(w.scal + 2, &one, sizeof(double),
                          hipMemcpyHostToDevice, st));
@@ -861,13 +878,17 @@ sgm_status sgm_matrix_destroy(sgm_matrix A) {
 }
 
 sgm_status sgm_matrix_info(sgm_matrix A, int64_t* n, int64_t* nnz,
-                           int64_t* sell_nnz) {
+                           int64_t* sell_nnz, int32_t* index_bytes) {
   SGM_API_BEGIN
   SGM_REQUIRE(A != nullptr, "matrix is NULL");
   const Matrix& M = *handle(A)->M;
   if (n) *n = M.n;
   if (nnz) *nnz = M.nnz;
   if (sell_nnz) *sell_nnz = M.fwd.nnz_padded;
+  if (index_bytes) {
+    index_bytes[0] = M.fwd.rcol ? 2 : 4;
+    index_bytes[1] = M.trn.rcol ? 2 : 4;
+  }
   return SGM_OK;
   SGM_API_END
 }

@@ -13,23 +13,42 @@ constexpr int kSlicesPerBlock = kSpmvBlock / kWave;
 // x, xprev and y are columns of a block of vectors with layout XV (row r of
 // a column at column base + XV.row_off(r)); the plain and residual
 // epilogues use contiguous vectors (column-major view).
-// IDX is int32_t (absolute columns) or int16_t (column - row).
+// IDX is int32_t (absolute columns) or int16_t (16-bit relative columns:
+// group base kbase[ptr[s] / 64 + w] + lane + offset).
 template <typename T, int EPI, typename IDX>
 __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
     const int64_t* __restrict__ ptr, const int32_t* __restrict__ width,
-    const IDX* __restrict__ col, const T* __restrict__ val, QView<T> XV,
-    const T* __restrict__ x, const T* __restrict__ xprev, T* __restrict__ y,
+    const IDX* __restrict__ col, const int32_t* __restrict__ kbase,
+    const T* __restrict__ val, QView<T> XV, const T* __restrict__ x,
+    const T* __restrict__ xprev, T* __restrict__ y,
     const double* __restrict__ b, double* __restrict__ part, int64_t n,
     int64_t nslices, const double* __restrict__ rec, int j) {
-  const int64_t s = (int64_t)blockIdx.x * kSlicesPerBlock + threadIdx.x / kWave;
+  // slice index is wavefront-uniform: its metadata comes in scalar loads
+  const int64_t s = (int64_t)blockIdx.x * kSlicesPerBlock +
+                    __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   const int lane = threadIdx.x % kWave;
   const int64_t r = s * kSlice + lane;
-  // column of an entry: absolute, or the row plus a 16-bit delta
-  const int32_t cb = sizeof(IDX) == 2 ? (int32_t)r : 0;
+  // the epilogue's own operands are loaded first, so their latency
+  // overlaps the matrix stream instead of following it
+  T xo = 0, xp = 0;
+  int64_t ro = 0;
+  double bb = 0.0;
+  if constexpr (EPI == EPI_MPK) {
+    if (r < n) {
+      ro = XV.row_off(r);
+      xo = x[ro];
+      if (xprev != nullptr) xp = xprev[ro];
+    }
+  } else if constexpr (EPI == EPI_RESID) {
+    if (r < n) bb = b[r];
+  }
   T sum = 0;
   if (s < nslices) {
-    const int64_t base = ptr[s] + lane;
+    const int64_t p0 = ptr[s];
+    const int64_t base = p0 + lane;
     const int w = width[s];
+    const int32_t* __restrict__ kb =
+        sizeof(IDX) == 2 ? kbase + (p0 >> 6) : nullptr;
     // Eight entries per pass: all index and value loads of the pass go out
     // together, then all eight x gathers.  Slots past the row's width
     // re-read its last entry (a valid address) and weigh it by zero.
@@ -40,7 +59,10 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
       for (int q = 0; q < 8; ++q) {
         const int kk = min(k + q, w - 1);
         const int64_t e = base + (int64_t)kk * kSlice;
-        c[q] = cb + col[e];
+        if constexpr (sizeof(IDX) == 2)
+          c[q] = kb[kk] + lane + (int32_t)col[e];
+        else
+          c[q] = col[e];
         v[q] = val[e];
       }
       T xv[8];
@@ -55,17 +77,16 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
     if (r < n) y[r] = sum;
   } else if constexpr (EPI == EPI_MPK) {
     if (r < n) {
-      const int64_t ro = XV.row_off(r);
       const T theta = (T)rec[3 * j], gamma = (T)rec[3 * j + 1],
               delta = (T)rec[3 * j + 2];
-      T v = sum - theta * x[ro];
-      if (xprev != nullptr) v = v - delta * xprev[ro];
+      T v = sum - theta * xo;
+      if (xprev != nullptr) v = v - delta * xp;
       y[ro] = v / gamma;
     }
   } else {  // EPI_RESID (float64): r = b - A x, partial sums of r^2
     double rr = 0.0;
     if (r < n) {
-      rr = b[r] - (double)sum;
+      rr = bb - (double)sum;
       y[r] = (T)rr;
     }
     double q = rr * rr;
@@ -162,13 +183,13 @@ inline unsigned g1(int64_t n) {
 template <typename T>
 void spmv_plain(const Sell& S, const T* val, const T* x, T* y,
                 hipStream_t st) {
-#define SGM_SPMV(IDX, colp)                                                    \
-  hipLaunchKernelGGL((k_spmv<T, EPI_PLAIN, IDX>), dim3(spmv_grid(S)),          \
-                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, val,       \
-                     colmajor_view<T>(nullptr, 0), x, (const T*)nullptr, y,    \
-                     (const double*)nullptr, (double*)nullptr, S.n, S.nslices, \
-                     (const double*)nullptr, 0)
-  if (S.dcol) SGM_SPMV(int16_t, S.dcol); else SGM_SPMV(int32_t, S.col);
+#define SGM_SPMV(IDX, colp)                                                   \
+  hipLaunchKernelGGL((k_spmv<T, EPI_PLAIN, IDX>), dim3(spmv_grid(S)),         \
+                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, S.kbase,  \
+                     val, colmajor_view<T>(nullptr, 0), x, (const T*)nullptr, \
+                     y, (const double*)nullptr, (double*)nullptr, S.n,        \
+                     S.nslices, (const double*)nullptr, 0)
+  if (S.rcol) SGM_SPMV(int16_t, S.rcol); else SGM_SPMV(int32_t, S.col);
 #undef SGM_SPMV
   SGM_CHECK_LAUNCH();
 }
@@ -179,11 +200,11 @@ void spmv_mpk(const Sell& S, const T* val, QView<T> Q, int jx, int jprev,
   const T* xp = jprev >= 0 ? (const T*)Q.col(jprev) : (const T*)nullptr;
 #define SGM_SPMV(IDX, colp)                                                   \
   hipLaunchKernelGGL((k_spmv<T, EPI_MPK, IDX>), dim3(spmv_grid(S)),           \
-                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, val, Q,   \
-                     (const T*)Q.col(jx), xp, Q.col(jy),                      \
+                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, S.kbase,  \
+                     val, Q, (const T*)Q.col(jx), xp, Q.col(jy),              \
                      (const double*)nullptr, (double*)nullptr, S.n,           \
                      S.nslices, rec, j)
-  if (S.dcol) SGM_SPMV(int16_t, S.dcol); else SGM_SPMV(int32_t, S.col);
+  if (S.rcol) SGM_SPMV(int16_t, S.rcol); else SGM_SPMV(int32_t, S.col);
 #undef SGM_SPMV
   SGM_CHECK_LAUNCH();
 }
@@ -194,11 +215,11 @@ int64_t spmv_resid(const Sell& S, const double* val, const double* x,
                    const double* b, double* r, double* part, hipStream_t st) {
 #define SGM_SPMV(IDX, colp)                                                   \
   hipLaunchKernelGGL((k_spmv<double, EPI_RESID, IDX>), dim3(spmv_grid(S)),    \
-                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, val,      \
-                     colmajor_view<double>(nullptr, 0), x,                    \
+                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, S.kbase,  \
+                     val, colmajor_view<double>(nullptr, 0), x,               \
                      (const double*)nullptr, r, b, part, S.n, S.nslices,      \
                      (const double*)nullptr, 0)
-  if (S.dcol) SGM_SPMV(int16_t, S.dcol); else SGM_SPMV(int32_t, S.col);
+  if (S.rcol) SGM_SPMV(int16_t, S.rcol); else SGM_SPMV(int32_t, S.col);
 #undef SGM_SPMV
   SGM_CHECK_LAUNCH();
   return spmv_grid(S);

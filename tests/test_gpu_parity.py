@@ -40,17 +40,26 @@ def cols_of(t, n, ld, k):
 
 # ------------------------------------------------------------------ SpMV
 
-@pytest.mark.parametrize("mk", [lambda: W.conv_diff_2d(64, 10.0),
-                                lambda: W.poisson_3d(23),
-                                lambda: W.banded_problem(3001, band=300)[0],
-                                # entries farther than 32767 from the
-                                # diagonal: 32-bit column indices
-                                lambda: W.banded_problem(70001, band=40000)[0]])
-def test_spmv_matches_csr_product(lib, mk):
+@pytest.mark.parametrize("mk,ibytes", [
+    (lambda: W.conv_diff_2d(64, 10.0), 2),
+    (lambda: W.poisson_3d(23), 2),
+    (lambda: W.banded_problem(3001, band=300)[0], 2),
+    # couplings 40,200 rows from the diagonal (one 200 x 201 plane), a
+    # ragged last slice: 16-bit offsets against the group bases still fit
+    (lambda: W.poisson_3d_box((3, 200, 201)), 2),
+    # random columns up to 40,000 either side of the diagonal: every slice
+    # position (k-th smallest column of 64 rows) still spans < 65536
+    (lambda: W.banded_problem(70001, band=40000)[0], 2),
+    # up to 70,000 either side: some slice position spans about 80,000
+    # columns, so 32-bit column indices
+    (lambda: W.banded_problem(140001, band=70000)[0], 4)])
+def test_spmv_matches_csr_product(lib, mk, ibytes):
     import torch
     A = mk()
     M = csr(A)
     G = lib.Matrix.from_csr(A)
+    info = G.info()
+    assert info["index_bytes"] == ibytes and info["index_bytes_t"] == ibytes
     x = np.random.default_rng(0).standard_normal(A.n)
     y = G.spmv(x).cpu().numpy()
     yr = M @ x
@@ -296,13 +305,38 @@ def test_solve_jacobi_variable_coefficients(lib):
     assert rel <= 1e-8
 
 
-def test_solve_wide_band_32bit_columns(lib):
-    """A matrix with entries up to 40000 from the diagonal keeps 32-bit
-    column indices in the matrix powers kernel and residual SpMV."""
-    A, b, _ = W.banded_problem(70001, seed=5, band=40000)
+@pytest.mark.parametrize("n,band,ibytes", [(70001, 40000, 2),
+                                            (140001, 70000, 4)])
+def test_solve_wide_band_columns(lib, n, band, ibytes):
+    """Random banded matrices with entries up to 40,000 or 70,000 from the
+    diagonal: the matrix powers kernel and residual SpMV read 16-bit
+    offsets against the group bases in the first case and 32-bit columns in
+    the second (a slice position spans more than 65535 columns)."""
+    A, b, _ = W.banded_problem(n, seed=5, band=band)
+    assert lib.Matrix.from_csr(A).info()["index_bytes"] == ibytes
     gpu, ref, rel = _compare_solve(lib, A, b, 16, 64, 1e-12)
     assert rel <= 1e-10
     assert list(gpu.s_hist) == ref.s_hist
+
+
+def test_solve_far_couplings_16bit_columns(lib):
+    """A 7-point stencil whose planes hold 40,200 rows (n = 120,600, not a
+    multiple of 64): the matrix powers kernel and residual SpMV read 16-bit
+    offsets against per-group bases.  One restart cycle against the
+    oracle: same block sizes, residual estimates to 1e-6."""
+    A = W.poisson_3d_box((3, 200, 201))
+    assert A.n % 64 != 0
+    b = W.rhs(A.n, 9)
+    G = lib.Matrix.from_csr(A)
+    assert G.info()["index_bytes"] == 2
+    kw = dict(s_max=16, restart=64, tol=1e-10)
+    gpu = lib.solve(G, b, max_restarts=0, **kw)
+    ref = o.solve(csr(A), b, opts=o.Options(max_restarts=0, **kw))
+    assert list(gpu.s_hist) == ref.s_hist
+    h, hr = np.asarray(gpu.res_hist), np.asarray(ref.res_hist)
+    assert h.shape == hr.shape and np.all(np.abs(h - hr) <= 1e-6 * hr)
+    x = gpu.x.cpu().numpy()
+    assert np.linalg.norm(x - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
 
 
 def test_solve_transpose(lib):

@@ -116,14 +116,23 @@ def conv_diff_2d(nx: int = 64, peclet: float = 10.0) -> Csr:
 
 def poisson_3d(nx: int = 128) -> Csr:
     """3D Poisson, 7-point (6, -1) on an nx^3 interior grid, Dirichlet."""
+    A = poisson_3d_box((nx, nx, nx))
+    A.name = f"poisson3d_{nx}"
+    return A
+
+
+def poisson_3d_box(shape) -> Csr:
+    """3D Poisson, 7-point (6, -1) on a box grid of the given shape (slowest
+    axis first), Dirichlet.  The couplings across the slowest axis lie one
+    plane (shape[1] * shape[2] rows) from the diagonal."""
     offs = [((0, 0, 0), 6.0)]
     for d in range(3):
         for s in (-1, 1):
             o = [0, 0, 0]
             o[d] = s
             offs.append((tuple(o), -1.0))
-    n, r, c, v = _stencil((nx, nx, nx), offs)
-    return _from_coo(n, r, c, v, f"poisson3d_{nx}")
+    n, r, c, v = _stencil(tuple(shape), offs)
+    return _from_coo(n, r, c, v, "poisson3d_" + "x".join(map(str, shape)))
 
 
 def laplace_2d(nx: int) -> Csr:
