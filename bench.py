@@ -160,11 +160,14 @@ def spmv_roofline(A, G, rs, vb, label):
     bytes nnz (vb + 4) + 4 (n + 1) + 2 vb n per launch over the average
     launch time (HIP events around every MPK launch); also the SELL
     format's own minimum, padded entries times (vb + index bytes) plus
-    x and y."""
+    x and y.  None when the solves made no matrix powers launch (they
+    converged inside the column-wise Ritz pre-phase)."""
     info = G.info()
     n_spmv = sum(r.info["n_spmv"] for r in rs)
     t_spmv = sum(r.info["t_spmv_ms"] for r in rs)
-    avg_ms = t_spmv / max(1, n_spmv)
+    if n_spmv == 0 or t_spmv <= 0:
+        return None  # converged inside the column-wise pre-phase
+    avg_ms = t_spmv / n_spmv
     alg = A.nnz * (vb + 4) + 4 * (A.n + 1) + 2 * vb * A.n
     fmt = info["sell_nnz"] * (vb + info["index_bytes"]) + 2 * vb * A.n
     ach = alg / (avg_ms * 1e-3) / 1e9
@@ -223,6 +226,8 @@ def study(args, np, torch, sgm, W):
                "precond": "none", "s_max": 200, "restart": 400,
                "caps": "float64: 5 restart cycles; float32-IR: 5 outer steps",
                "rhs": "N(0,1) seed 5"}
+    if args.mode == "fp64":
+        modes = [m for m in modes if m[0].startswith("fp64")]
     cfg.update({"n": A.n, "nnz": A.nnz, "basis": "scaled_newton",
                 "tol": 1e-10, "x0": "zero"})
     G = sgm.Matrix.from_csr(A)
@@ -262,8 +267,10 @@ def study(args, np, torch, sgm, W):
             out[mname]["speedup_vs_fp64"] = round(
                 out["fp64"]["ms"] / out[mname]["ms"], 3)
     out["roofline"] = spmv_roofline(A, G, infos["fp64"], 8, "double")
-    out["roofline_fp32"] = spmv_roofline(A, G, infos["fp32_ir"], 4, "float")
-    if name == "aniso2d_4096":
+    if "fp32_ir" in infos:
+        out["roofline_fp32"] = spmv_roofline(A, G, infos["fp32_ir"], 4,
+                                             "float")
+    if name == "aniso2d_4096" and args.mode != "fp64":
         # backward solve for the gradient w.r.t. b (float32-IR, same caps)
         bt = torch.tensor(b_host, device="cuda", requires_grad=True)
         vals = torch.tensor(A.val, device="cuda")
@@ -379,6 +386,15 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy_mb > 0:
+        nel = args.calibrate_copy_mb * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
+        log(f"[bench] calibration copy of {args.calibrate_copy_mb} MiB done")
     if args.workload != "poisson3d_128":
         print(json.dumps(study(args, np, torch, sgm, W)), flush=True)
         return
@@ -407,13 +423,6 @@ def main():
                             ("fp32_ir_monomial_pyth", o32mp)],
              "fp64": [("fp64", o64)], "fp32_ir": [("fp32_ir", o32)]}[args.mode]
 
-    if args.calibrate_copy_mb > 0:
-        nel = args.calibrate_copy_mb * (1 << 20) // 8
-        src = torch.ones(nel, dtype=torch.float64, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"[bench] calibration copy of {args.calibrate_copy_mb} MiB done")
 
     def run(opts):
         t0 = time.perf_counter()

@@ -306,10 +306,14 @@ void launch_reduce(const double* part, int64_t nchunks, int ma, int nb,
 // MODE_TRSM:   B(:, 0:p) = B(:, 0:p) M(0:p, 0:p) in place, M upper
 //              triangular (tiles below the diagonal are skipped).
 // A wavefront's 16*MT rows (16, 32 or 64, aligned) lie in one row panel.
+// M is staged in LDS (negated for the update) in chunks of kc rows; when it
+// fits whole it is staged once per workgroup, which then walks its row
+// blocks without further barriers.  Wide blocks take BLOCK = 512 or 1024
+// threads, so the wavefronts of a CU share one staged copy.
 enum { MODE_UPDATE = 0, MODE_TRSM = 1 };
 
-template <typename T, int NT, int MT, int MODE, bool GRAM>
-__global__ __launch_bounds__(kBlock) void k_update(
+template <typename T, int NT, int MT, int MODE, bool GRAM, int BLOCK = kBlock>
+__global__ __launch_bounds__(BLOCK) void k_update(
     QView<T> Q, int a0, int ka, int b0c, int nc,
     const double* __restrict__ M, int ldm, const int* __restrict__ ncount,
     int64_t nrows, int kc, double* __restrict__ part) {
@@ -326,11 +330,11 @@ __global__ __launch_bounds__(kBlock) void k_update(
   const int ka4 = (kae + 3) & ~3;
   const bool single = ka4 <= kc;
   const int64_t rows_per_wave = 16 * MT;
-  const int64_t rows_per_block = rows_per_wave * (kBlock / kWave);
+  const int64_t rows_per_block = rows_per_wave * (BLOCK / kWave);
   const int64_t nblocks = (nrows + rows_per_block - 1) / rows_per_block;
 
   auto stage = [&](int k0) {
-    for (int e = threadIdx.x; e < kc * W16; e += kBlock) {
+    for (int e = threadIdx.x; e < kc * W16; e += BLOCK) {
       const int kk = e / W16, cc = e % W16;
       const int k = k0 + kk;
       double v = 0.0;
@@ -477,7 +481,7 @@ __global__ __launch_bounds__(kBlock) void k_update(
     __syncthreads();
     double* red = reinterpret_cast<double*>(smem_raw);
     constexpr int NE = NG * 4;
-    for (int w = kBlock / kWave - 1; w >= 1; --w) {
+    for (int w = BLOCK / kWave - 1; w >= 1; --w) {
       if (wave == w) {
 #pragma unroll
         for (int t = 0; t < NG; ++t)
@@ -485,7 +489,7 @@ __global__ __launch_bounds__(kBlock) void k_update(
           for (int q = 0; q < 4; ++q) {
             const int e = (t * 4 + q) * kWave + lane;
             double v = (double)gacc[t][q];
-            if (w < kBlock / kWave - 1) v += red[e];
+            if (w < BLOCK / kWave - 1) v += red[e];
             red[e] = v;
           }
       }
@@ -1116,6 +1120,7 @@ __global__ __launch_bounds__(kBlock) void k_col_scale(
 // About two workgroups per CU (256 CUs): one full wave of workgroups, few
 // enough partials that their reduction stays cheap.
 constexpr int kTargetGroups = 512;
+constexpr int kNumCUs = 256;  // MI355X compute units
 
 int pick_chunks(int target_groups, int ntiles, int64_t nbatches,
                 int64_t per_chunk, const Partials& P) {
@@ -1192,15 +1197,19 @@ void gemm_tn(QView<const T> Q, int a0, int ma, int b0, int nb,
 namespace {
 
 constexpr int kLdsBudget = 64 * 1024;
+// LDS of one workgroup for the staged M of blocks wider than 64 columns:
+// most of gfx950's 160 KiB, so M stays whole for i + s up to about 150
+// (float64) or 300 (float32) at s = 128.
+constexpr int kWideLdsBudget = 152 * 1024;
 
-template <typename T, int NT, int MT, int MODE, bool GRAM>
-void launch_update(QView<T> Q, int a0, int ka, int b0, int nc,
-                   const double* M, int ldm, const int* ncount, int64_t nrows,
-                   double* G, int ldg, Partials& P, hipStream_t st,
-                   int target_groups = kTargetGroups) {
+template <typename T, int NT, int MT, int MODE, bool GRAM, int BLOCK>
+void launch_update_b(QView<T> Q, int a0, int ka, int b0, int nc,
+                     const double* M, int ldm, const int* ncount,
+                     int64_t nrows, double* G, int ldg, Partials& P,
+                     hipStream_t st, int lds_budget, int64_t target_groups) {
   const int W16 = NT * 16;
   const int ka4 = (ka + 3) & ~3;
-  int kc = kLdsBudget / (W16 * (int)sizeof(T));
+  int kc = lds_budget / (W16 * (int)sizeof(T));
   kc &= ~3;
   if (kc > ka4) kc = ka4 < 4 ? 4 : ka4;
   size_t lds = (size_t)kc * W16 * sizeof(T);
@@ -1208,7 +1217,7 @@ void launch_update(QView<T> Q, int a0, int ka, int b0, int nc,
     const size_t red = (size_t)(NT * (NT + 1) / 2) * 4 * kWave * sizeof(double);
     if (red > lds) lds = red;
   }
-  const int64_t rows_per_block = 16 * MT * (kBlock / kWave);
+  const int64_t rows_per_block = 16 * MT * (BLOCK / kWave);
   const int64_t nblocks = ceil_div(nrows, rows_per_block);
   int64_t grid = nblocks < target_groups ? nblocks : target_groups;
   if (grid < 1) grid = 1;
@@ -1216,11 +1225,34 @@ void launch_update(QView<T> Q, int a0, int ka, int b0, int nc,
     grid = P.cap / ((int64_t)nc * nc);
     if (grid < 1) throw Error{SGM_EINVAL, "partial scratch too small"};
   }
-  hipLaunchKernelGGL((k_update<T, NT, MT, MODE, GRAM>), dim3((unsigned)grid),
-                     dim3(kBlock), lds, st, Q, a0, ka, b0, nc, M, ldm, ncount,
-                     nrows, kc, GRAM ? P.buf : (double*)nullptr);
+  hipLaunchKernelGGL((k_update<T, NT, MT, MODE, GRAM, BLOCK>),
+                     dim3((unsigned)grid), dim3(BLOCK), lds, st, Q, a0, ka,
+                     b0, nc, M, ldm, ncount, nrows, kc,
+                     GRAM ? P.buf : (double*)nullptr);
   SGM_CHECK_LAUNCH();
   if (GRAM) launch_reduce(P.buf, grid, nc, nc, G, ldg, 1, st);
+}
+
+// Blocks up to 64 columns: 256-thread workgroups, a 64 KiB chunk of M.
+// Wider blocks: one workgroup per CU holding (most of) M in LDS, with 1024
+// threads while the kernel fits four wavefronts per SIMD (at most 128
+// registers each: up to 72 accumulator registers), else 512.
+template <typename T, int NT, int MT, int MODE, bool GRAM>
+void launch_update(QView<T> Q, int a0, int ka, int b0, int nc,
+                   const double* M, int ldm, const int* ncount, int64_t nrows,
+                   double* G, int ldg, Partials& P, hipStream_t st,
+                   int target_groups = kTargetGroups) {
+  if constexpr (NT <= 4 || GRAM) {
+    launch_update_b<T, NT, MT, MODE, GRAM, kBlock>(
+        Q, a0, ka, b0, nc, M, ldm, ncount, nrows, G, ldg, P, st, kLdsBudget,
+        target_groups);
+  } else {
+    constexpr int acc_regs = NT * MT * 4 * (int)sizeof(T) / 4;
+    constexpr int B = acc_regs <= 72 ? 1024 : 512;
+    launch_update_b<T, NT, MT, MODE, GRAM, B>(
+        Q, a0, ka, b0, nc, M, ldm, ncount, nrows, G, ldg, P, st,
+        kWideLdsBudget, kNumCUs);
+  }
 }
 
 }  // namespace
