@@ -125,7 +125,12 @@ constexpr int kBlock = 256;  // 4 wavefronts per workgroup
 // 4-vector, and MFMA step t pairs row 4g + t of A with the same row of B.
 // A 16-row batch never straddles a row panel, so one row offset per batch
 // serves every column.
-template <typename T, int MT, int NT, int WT>
+// SYM (a Gram matrix of more than 64 columns: the same columns on both
+// sides): only the 16x16 tiles on and above the diagonal are formed and
+// stored; the reduction mirrors the rest.  A compile-time switch: as a
+// run-time test inside the unrolled MFMA loops it raised the register
+// count of other tile shapes.
+template <typename T, int MT, int NT, int WT, bool SYM>
 __global__ __launch_bounds__(kBlock) void k_gemm_tn(
     QView<const T> Q, int a0, int ma, int b0c, int nb,
     const int* __restrict__ ncount, int64_t nbatches, int wtiles_n,
@@ -145,8 +150,12 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(
   const int nbe = ncount ? min(nb, *ncount) : nb;
   const int64_t b0 = nbatches * chunk / chunks;
   const int64_t b1 = nbatches * (chunk + 1) / chunks;
-  // M tiles of this wave tile with a valid column (0 for a spare wavefront)
-  const int mt_live = t < n_wtiles ? min(MT, (ma - m0 + 15) / 16) : 0;
+  // M tiles of this wave tile with a valid column (0 for a spare wavefront,
+  // and for a wave tile wholly below the diagonal of a symmetric product)
+  const int tm0 = m0 / 16, tn0 = n0 / 16;
+  const bool below = SYM && tm0 > tn0 + NT - 1;
+  const int mt_live =
+      t < n_wtiles && !below ? min(MT, (ma - m0 + 15) / 16) : 0;
 
   // per-lane column offsets; a column past the end reads column a0 / b0c
   int64_t oa[MT], ob[NT];
@@ -191,7 +200,10 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(
         for (int i = 0; i < MT; ++i) {
           if (i >= mt_live) continue;
 #pragma unroll
-          for (int j = 0; j < NT; ++j) acc[i][j] = mfma(af[i][q], bf[j][q], acc[i][j]);
+          for (int j = 0; j < NT; ++j) {
+            if (SYM && tm0 + i > tn0 + j) continue;  // mirrored tile
+            acc[i][j] = mfma(af[i][q], bf[j][q], acc[i][j]);
+          }
         }
       if (more) {
 #pragma unroll
@@ -234,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(
         for (int q = 0; q < 4; ++q) {
           const int row = m0 + i * 16 + drow<T>(g, q);
           const int col = n0 + j * 16 + c16;
-          if (row < ma && col < nb) {
+          if (row < ma && col < nb && !(SYM && tm0 + i > tn0 + j)) {
             double v = (double)acc[i][j][q];
             if constexpr (RP > 1)
               v += red[(wt * NE + (i * NT + j) * 4 + q) * kWave + lane];
@@ -1136,12 +1148,12 @@ int pick_chunks(int target_groups, int ntiles, int64_t nbatches,
   return (int)target;
 }
 
-template <typename T, int MT, int NT, int WT>
+template <typename T, int MT, int NT, int WT, bool SYM = false>
 void launch_gemm_tn(QView<const T> Q, int a0, int ma, int b0, int nb,
                     const int* ncount, int64_t nbatches, int wtiles_n,
                     int n_wtiles, int ngroups, int chunks, double* part,
                     hipStream_t st) {
-  hipLaunchKernelGGL((k_gemm_tn<T, MT, NT, WT>), dim3(chunks * ngroups),
+  hipLaunchKernelGGL((k_gemm_tn<T, MT, NT, WT, SYM>), dim3(chunks * ngroups),
                      dim3(kBlock), 0, st, Q, a0, ma, b0, nb, ncount, nbatches,
                      wtiles_n, n_wtiles, ngroups, chunks, part);
   SGM_CHECK_LAUNCH();
@@ -1177,6 +1189,21 @@ void gemm_tn(QView<const T> Q, int a0, int ma, int b0, int nb,
   groups = groups < 256 ? 256 : (groups > 1024 ? 1024 : groups);
   const int chunks =
       pick_chunks((int)groups, ngroups, nbatches, (int64_t)ma * nb, P);
+  // A float64 Gram matrix wider than 64 columns: 64 x 64 wave tiles, one
+  // per wavefront, on and above the diagonal only.  (Measured at 128
+  // columns over 7M rows: 4.1 ms against 4.5 ms for the full product in
+  // 32 x 64 tiles.  The kernel is bound by fetching its operands, not by
+  // the matrix cores, so the larger tiles gain more than the skipped
+  // tiles; in float32 the full product measured faster.)
+  if (sizeof(T) == 8 && a0 == b0 && ma == nb && nt_all > 4) {
+    const int wn = (nt_all + 3) / 4, wm = (mt_all + 3) / 4;
+    const int chunks_s =
+        pick_chunks((int)groups, wm * wn, nbatches, (int64_t)ma * nb, P);
+    launch_gemm_tn<T, 4, 4, 1, true>(Q, a0, ma, b0, nb, ncount, nbatches, wn,
+                                     wm * wn, wm * wn, chunks_s, P.buf, st);
+    launch_reduce(P.buf, chunks_s, ma, nb, C, ldc, 1, st);
+    return;
+  }
 #define SGM_GT(mt, nt, wt)                                                  \
   if (MT == mt && NT == nt && WT == wt) {                                   \
     launch_gemm_tn<T, mt, nt, wt>(Q, a0, ma, b0, nb, ncount, nbatches,      \
