@@ -70,9 +70,14 @@ int basis_cols(int m, int vb) {
   }
 }
 
-int64_t part_cap(int m, int smax) {
+// Partial sums of the grid reductions: room for 512 row chunks of the
+// widest product ((m + 1) x s_max), so the products of wide blocks keep two
+// workgroups per CU (fewer chunks when n has fewer 64-row panels).
+int64_t part_cap(int m, int smax, int64_t n) {
+  int64_t chunks = n / kPanel;
+  chunks = chunks < 8 ? 8 : (chunks > 512 ? 512 : chunks);
   int64_t a = (int64_t)1 << 22;
-  int64_t b = (int64_t)16 * (m + 1) * smax;
+  int64_t b = chunks * (m + 1) * smax;
   return a > b ? a : b;
 }
 
@@ -92,7 +97,7 @@ void layout(Arena& a, Work& w, int64_t n, int64_t sell_nnz, int m, int smax,
     w.jac64 = a.take<double>(sell_nnz);
     w.jac32 = a.take<float>(sell_nnz);
   }
-  w.P.cap = part_cap(m, smax);
+  w.P.cap = part_cap(m, smax, n);
   w.P.buf = a.take<double>(w.P.cap);
   const int64_t ws = (int64_t)w.ldw * smax, ss = (int64_t)smax * smax;
   w.W = a.take<double>(ws);
@@ -794,10 +799,10 @@ size_t solve_ws_bytes(const Matrix& M, const sgm_opts& o) {
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Workspace of the stand-alone block orthogonalisation.
-void block_layout(Arena& a, Work& w, int i, int s) {
+void block_layout(Arena& a, Work& w, int i, int s, int64_t n_rows) {
   w.ldw = std::max(i, 1) + s;  // room for [R2; Gram] of the Pythagorean pass
   w.lds = s;
-  w.P.cap = std::max<int64_t>((int64_t)1 << 22, (int64_t)16 * (i + 1) * s);
+  w.P.cap = part_cap(i, s, n_rows);
   w.P.buf = a.take<double>(w.P.cap);
   const int64_t ws = (int64_t)w.ldw * s, ss = (int64_t)s * s;
   w.W = a.take<double>(ws);
@@ -1050,11 +1055,10 @@ sgm_status sgm_mpk(sgm_matrix A, int transpose, sgm_precision precision,
 }
 
 size_t sgm_block_ws_size(int64_t n_rows, int32_t i, int32_t s) {
-  (void)n_rows;
   if (i < 1 || s < 1) return 0;
   Arena a;
   Work w;
-  block_layout(a, w, i, s);
+  block_layout(a, w, i, s, n_rows);
   return a.off + 256;
 }
 
@@ -1079,7 +1083,7 @@ sgm_status sgm_block_orth(sgm_precision precision, int64_t n_rows, void* Q,
   a.base = reinterpret_cast<char*>(
       round_up(reinterpret_cast<int64_t>(ws), 256));
   Work w;
-  block_layout(a, w, i, s);
+  block_layout(a, w, i, s, n_rows);
   hipStream_t st = as_stream(stream);
   const bool f32 = precision == SGM_FP32_IR;
   const double om = omega > 0 ? omega : default_omega(f32);

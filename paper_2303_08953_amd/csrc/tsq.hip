@@ -256,6 +256,125 @@ __global__ __launch_bounds__(kBlock) void k_gemm_tn(
   }
 }
 
+// ------------------------------------------------------------- wide A^T B
+// C = Q(:, a0:a0+ma)^T Q(:, b0:b0+nb) for blocks wider than 64 columns,
+// where the kernel above is bound by every wavefront fetching its own
+// operands (measured at 129 x 128 over 7M rows: 37-51 of the 78.6 TFLOP/s
+// float64 peak).  The output is cut into blocks of 144 x 128 (9 x 8 MFMA
+// tiles); a 512-thread workgroup covers one block over one row chunk.
+// Each 16-row batch of the block's 144 + 128 columns is loaded once per
+// workgroup into LDS, double-buffered, and wavefront w forms the nine tiles
+// of output column tile w from there.  LDS holds a batch column by column
+// with a stride of 17 elements, so the 16 lanes of an operand read hit
+// distinct banks.  MFMA step q pairs row 4q + g of both operands (lane
+// group g = lane / 16).  Columns past ma / nbe read a valid column; their
+// results are not stored (rows past ma) or stored as zero (columns past
+// nbe), as in the kernel above.  Grid: nblocks * chunks workgroups (chunks
+// a multiple of 8), decoded XCD-aware like the kernel above.
+constexpr int kWM = 9, kWN = 8;            // tiles per output block
+constexpr int kWCols = 16 * (kWM + kWN);   // 272 columns per batch
+constexpr int kWStride = 17;               // LDS column stride (elements)
+constexpr int kWBlock = kWN * kWave;       // one wavefront per column tile
+
+template <typename T>
+__global__ __launch_bounds__(kWBlock) void k_gemm_tn_wide(
+    QView<const T> Q, int a0, int ma, int b0c, int nb,
+    const int* __restrict__ ncount, int64_t nbatches, int nbn, int nblk,
+    int chunks, double* __restrict__ part) {
+  typedef typename Vec4<T>::type V;
+  constexpr int EPV = 16 / (int)sizeof(T);  // elements per 16-byte load
+  constexpr int VPC = 16 / EPV;             // loads per 16-row column batch
+  constexpr int NV = kWCols * VPC;          // loads per batch
+  constexpr int NVT = (NV + kWBlock - 1) / kWBlock;
+  constexpr int LBUF = kWCols * kWStride;   // elements per LDS buffer
+  typedef T vec_t __attribute__((ext_vector_type(EPV)));
+  extern __shared__ char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int g = lane / 16, c16 = lane % 16;
+  const int id = blockIdx.x;
+  const int xcd = id % 8, slot = id / 8;
+  const int blk = slot % nblk;
+  const int chunk = (slot / nblk) * 8 + xcd;
+  const int m0 = (blk / nbn) * 16 * kWM, n0 = (blk % nbn) * 16 * kWN;
+  const int nbe = ncount ? min(nb, *ncount) : nb;
+  const int64_t bt0 = nbatches * chunk / chunks;
+  const int64_t bt1 = nbatches * (chunk + 1) / chunks;
+
+  // column offset in Q of batch column `col` (A columns, then B columns)
+  auto qcol = [&](int col) -> int64_t {
+    int c;
+    if (col < 16 * kWM) {
+      c = m0 + col;
+      c = a0 + (c < ma ? c : 0);
+    } else {
+      c = n0 + col - 16 * kWM;
+      c = b0c + (c < nbe ? c : 0);
+    }
+    return (int64_t)c * Q.cstride;
+  };
+  vec_t stage[NVT];
+  auto gload = [&](int64_t bt) {
+    const T* rb = Q.base + Q.row_off(bt * 16);
+#pragma unroll
+    for (int q = 0; q < NVT; ++q) {
+      const int e = threadIdx.x + kWBlock * q;
+      if (e < NV)
+        stage[q] = *reinterpret_cast<const vec_t*>(rb + qcol(e / VPC) +
+                                                   (e % VPC) * EPV);
+    }
+  };
+  auto lstore = [&](int buf) {
+    T* L = lds + buf * LBUF;
+#pragma unroll
+    for (int q = 0; q < NVT; ++q) {
+      const int e = threadIdx.x + kWBlock * q;
+      if (e < NV) {
+        T* d = L + (e / VPC) * kWStride + (e % VPC) * EPV;
+#pragma unroll
+        for (int u = 0; u < EPV; ++u) d[u] = stage[q][u];
+      }
+    }
+  };
+
+  V acc[kWM];
+#pragma unroll
+  for (int i = 0; i < kWM; ++i) acc[i] = vzero<V>();
+  int buf = 0;
+  if (bt0 < bt1) {
+    gload(bt0);
+    lstore(0);
+  }
+  __syncthreads();
+  for (int64_t bt = bt0; bt < bt1; ++bt) {
+    const bool more = bt + 1 < bt1;
+    if (more) gload(bt + 1);
+    const T* L = lds + buf * LBUF;
+    const T* Lb = L + (16 * kWM + wave * 16 + c16) * kWStride + g;
+    const T* La = L + c16 * kWStride + g;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T bv = Lb[4 * q];
+#pragma unroll
+      for (int i = 0; i < kWM; ++i)
+        acc[i] = mfma(La[i * 16 * kWStride + 4 * q], bv, acc[i]);
+    }
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  double* out = part + (int64_t)chunk * ma * nb;
+  const int col = n0 + wave * 16 + c16;
+#pragma unroll
+  for (int i = 0; i < kWM; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = m0 + i * 16 + drow<T>(g, r);
+      if (row < ma && col < nb)
+        out[(int64_t)col * ma + row] = col < nbe ? (double)acc[i][r] : 0.0;
+    }
+}
+
 // C(i, j) = sum over chunks of part[c][j * ma + i]; with sym, entries below
 // the diagonal 16x16 tiles are read from the mirrored upper entry.  One
 // workgroup of 16 wavefronts per 64 consecutive outputs: wavefront w sums
@@ -1189,6 +1308,25 @@ void gemm_tn(QView<const T> Q, int a0, int ma, int b0, int nb,
   groups = groups < 256 ? 256 : (groups > 1024 ? 1024 : groups);
   const int chunks =
       pick_chunks((int)groups, ngroups, nbatches, (int64_t)ma * nb, P);
+  if (mt_all > 4 && nt_all > 6 && !(a0 == b0 && ma == nb)) {
+    // more than 64 rows and 96 columns, not a Gram matrix: the LDS-shared
+    // kernel, whose 144 x 128 blocks are then mostly full (measured in the
+    // 192^3 solve at 129 x 128: 4.6 against 6.6 ms in float64, 2.4 against
+    // 3.6 ms in float32; a one-row product would waste 8 of its 9 row
+    // tiles)
+    const int nbm = (ma + 16 * kWM - 1) / (16 * kWM);
+    const int nbn = (nb + 16 * kWN - 1) / (16 * kWN);
+    const int nblk = nbm * nbn;
+    const int chunks_w =
+        pick_chunks(2 * kNumCUs, nblk, nbatches, (int64_t)ma * nb, P);
+    const size_t lds = (size_t)2 * kWCols * kWStride * sizeof(T);
+    hipLaunchKernelGGL(k_gemm_tn_wide<T>, dim3(chunks_w * nblk),
+                       dim3(kWBlock), lds, st, Q, a0, ma, b0, nb, ncount,
+                       nbatches, nbn, nblk, chunks_w, P.buf);
+    SGM_CHECK_LAUNCH();
+    launch_reduce(P.buf, chunks_w, ma, nb, C, ldc, 0, st);
+    return;
+  }
   // A float64 Gram matrix wider than 64 columns: 64 x 64 wave tiles, one
   // per wavefront, on and above the diagonal only.  (Measured at 128
   // columns over 7M rows: 4.1 ms against 4.5 ms for the full product in
