@@ -511,7 +511,7 @@ def main():
     out["roofline"] = {
         "kernel": f"k_spmv<{'double' if vb == 8 else 'float'}, EPI_MPK, "
                   "int16_t> (SELL-C-64 SpMV of the matrix powers kernel, "
-                  "16-bit column deltas; achieved is on the CSR bytes)",
+                  "16-bit relative columns; achieved is on the CSR bytes)",
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
