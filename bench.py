@@ -39,6 +39,8 @@ line; no CPU baseline, whose bounded sample would not fit in minutes):
                 restart 400, no preconditioner (condition ~1e7): float64 and
                 float32-IR with capped restarts (it does not reach 1e-10 in
                 minutes), plus the backward solve for the gradient w.r.t. b;
+                --grid N and --max-cycles C run the same family on N^2
+                with C cycles;
   banded_1m     random banded nonsymmetric n = 1M, 27 nonzeros per row:
                 the differentiable solve to 1e-12, forward and backward
                 (adjoint solve + gradient w.r.t. the CSR values).
@@ -208,11 +210,13 @@ def study(args, np, torch, sgm, W):
                          " velocity (20,10,5) upwind, Dirichlet",
                "precond": "jacobi (right)", "s_max": 128, "restart": 256,
                "rhs": "N(0,1) seed 3"}
-    else:  # aniso2d_4096
-        A = W.aniso_diffusion_2d(4096)
+    else:  # aniso2d_4096 (or --grid N: the same matrix family on N^2)
+        grid = args.grid or 4096
+        cyc = args.max_cycles or 5
+        A = W.aniso_diffusion_2d(grid)
         b_host = W.rhs(A.n, 5)
-        base = dict(s_max=200, restart=400, tol=1e-10, max_restarts=4)
-        b32 = dict(base, precision="fp32_ir", inner_tol=1e-6, max_outer=5,
+        base = dict(s_max=200, restart=400, tol=1e-10, max_restarts=cyc - 1)
+        b32 = dict(base, precision="fp32_ir", inner_tol=1e-6, max_outer=cyc,
                    max_restarts=1000)
         modes = [("fp64", base), ("fp32_ir", b32),
                  ("fp64_monomial_prephase", dict(base, prephase="monomial")),
@@ -220,11 +224,12 @@ def study(args, np, torch, sgm, W):
                   dict(b32, prephase="monomial")),
                  ("fp32_ir_monomial_no_estimator",
                   dict(b32, prephase="monomial", use_estimator=False))]
-        cfg = {"workload": name,
-               "matrix": "2D anisotropic diffusion 5-point 4096^2, "
+        cfg = {"workload": f"aniso2d_{grid}",
+               "matrix": f"2D anisotropic diffusion 5-point {grid}^2, "
                          "K = R(30deg) diag(1, 1e-3) R^T, K_xy dropped",
                "precond": "none", "s_max": 200, "restart": 400,
-               "caps": "float64: 5 restart cycles; float32-IR: 5 outer steps",
+               "caps": f"float64: {cyc} restart cycles; float32-IR: {cyc} "
+                       "outer steps",
                "rhs": "N(0,1) seed 5"}
     if args.mode == "fp64":
         modes = [m for m in modes if m[0].startswith("fp64")]
@@ -259,14 +264,18 @@ def study(args, np, torch, sgm, W):
            "ms_per_step": round(total_ms / max(1, args.steps), 3),
            "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "data": "synthetic",
-           "value": round(float(np.mean(per["fp64"])), 3), "dtype": "f64",
            "config": cfg}
     for mname, _ in modes:
         out[mname] = solve_summary(sgm, infos[mname], per[mname], 1e-10)
-        if mname != "fp64":
+        if mname != "fp64" and "fp64" in per:
             out[mname]["speedup_vs_fp64"] = round(
                 out["fp64"]["ms"] / out[mname]["ms"], 3)
-    out["roofline"] = spmv_roofline(A, G, infos["fp64"], 8, "double")
+    prim = "fp64" if "fp64" in infos else modes[0][0]
+    vb = 8 if prim.startswith("fp64") else 4
+    out["value"] = round(float(np.mean(per[prim])), 3)
+    out["dtype"] = "f64" if vb == 8 else "f32/f64"
+    out["roofline"] = spmv_roofline(A, G, infos[prim], vb,
+                                    "double" if vb == 8 else "float")
     if "fp32_ir" in infos:
         out["roofline_fp32"] = spmv_roofline(A, G, infos["fp32_ir"], 4,
                                              "float")
@@ -279,9 +288,11 @@ def study(args, np, torch, sgm, W):
         xg = sgm.sstep_solve(vals, bt, G, **o)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        log(f"[bench] differentiable forward: {(t1 - t0) * 1e3:.0f} ms")
         (0.5 * (xg ** 2).sum()).backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        log(f"[bench] backward: {(t2 - t1) * 1e3:.0f} ms")
         out["fp32_ir_with_backward"] = {
             "forward_ms": round((t1 - t0) * 1e3, 1),
             "backward_ms": round((t2 - t1) * 1e3, 1),
@@ -369,6 +380,11 @@ def main():
                              "banded_1m"])
     ap.add_argument("--mode", choices=["both", "fp64", "fp32_ir", "all"],
                     default="all")
+    ap.add_argument("--grid", type=int, default=0,
+                    help="aniso2d_4096 only: grid size N (N^2 unknowns)")
+    ap.add_argument("--max-cycles", type=int, default=0,
+                    help="aniso2d_4096 only: restart cycles (float64) and "
+                         "outer steps (float32-IR), default 5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="run one plain device copy of this size (for the "
