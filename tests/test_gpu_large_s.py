@@ -31,8 +31,29 @@ def cols_of(t, n, ld, k):
     return t.cpu().numpy().reshape(k, ld)[:, :n].T
 
 
-def _check_block(lib, Qi, V, omega=None):
-    """block_orth on [Qi, V] (GPU, in place) against the oracle."""
+def _sensitivity(Qi, V, om, ref, trials=3):
+    """How far the oracle's own Q_k, R_top and R_kk move when V is perturbed
+    by one unit roundoff (relative, random): the rounding-level spread a
+    different summation order may show.  None if the accepted size moves."""
+    rng = np.random.default_rng(11)
+    dq = dt = dk = 0.0
+    for _ in range(trials):
+        Vp = V * (1 + 2.0 ** -53 * rng.standard_normal(V.shape))
+        rp = o.block_orth(np.asfortranarray(Qi.copy()), Qi.shape[1], Vp, om)
+        if rp.p != ref.p:
+            return None
+        dq = max(dq, np.abs(rp.Qk - ref.Qk).max())
+        dt = max(dt, np.abs(rp.R_top - ref.R_top).max())
+        dk = max(dk, np.abs(rp.R_kk - ref.R_kk).max())
+    return dq, dt, dk
+
+
+def _check_block(lib, Qi, V, omega=None, spread=None):
+    """block_orth on [Qi, V] (GPU, in place) against the oracle.  With
+    spread = (dq, dt, dk) from _sensitivity, Q_k and R may differ by up to
+    100x the oracle's own response to a one-roundoff perturbation of V (for
+    ill-conditioned blocks, where rounding alone moves the last columns);
+    the accepted size and the orthogonality are checked exactly as always."""
     import torch
     n, i = Qi.shape
     s = V.shape[1]
@@ -43,12 +64,13 @@ def _check_block(lib, Qi, V, omega=None):
     p, Rt, Rk = lib.block_orth(Qd, n, ld, i, s, omega=om)
     assert p == ref.p, (p, ref.p)
     Qg = cols_of(Qd, n, ld, i + s)
+    dq, dt, dk = spread if spread is not None else (0.0, 0.0, 0.0)
     if p > 0:
-        assert np.abs(Qg[:, i:i + p] - ref.Qk).max() <= 1e-9
+        assert np.abs(Qg[:, i:i + p] - ref.Qk).max() <= max(1e-9, 100 * dq)
         assert (np.abs(Rt[:, :p] - ref.R_top).max()
-                <= 1e-9 * max(1.0, np.abs(ref.R_top).max()))
+                <= max(1e-9 * max(1.0, np.abs(ref.R_top).max()), 100 * dt))
         assert (np.abs(np.triu(Rk[:p, :p]) - ref.R_kk).max()
-                <= 1e-9 * np.abs(ref.R_kk).max())
+                <= max(1e-9 * np.abs(ref.R_kk).max(), 100 * dk))
         assert o.loo(Qg[:, :i + p]) <= 1e-12
     return p, ref
 
@@ -68,21 +90,27 @@ def test_block_orth_wide_full_rank(lib, i, s):
     assert p == s
 
 
-@pytest.mark.parametrize("s", [128, 200])
-def test_block_orth_wide_krylov_truncates(lib, s):
+@pytest.mark.parametrize("i,s", [(33, 128), (33, 200), (129, 128),
+                                 (129, 200)])
+def test_block_orth_wide_krylov_truncates(lib, i, s):
     """A long scaled Newton MPK block with the 8 shifts of a short pre-phase
     reused cyclically: the basis becomes ill-conditioned and partial
-    CholQR truncates it; the GPU keeps the same number of columns."""
+    CholQR truncates it; the GPU keeps the same number of columns.  With
+    129 prior columns the second projection runs the LDS-shared kernel
+    with its output columns masked to the first pass's accepted count."""
     A = W.conv_diff_2d(64, 10.0)
     M = csr(A)
     b = W.rhs(A.n, 2)
-    i = 33
     r = o.solve(M, b, opts=o.Options(s_max=8, restart=i - 1, max_restarts=0,
                                      tol=1e-300, record=True))
     Qi = r.trace["Q_first_cycle"][:, :i]
     V = o._Engine(M, o.Options()).mpk(Qi[:, i - 1], r.shifts, s)
     assert np.all(np.isfinite(V))
-    p, ref = _check_block(lib, Qi, V)
+    om = o.default_omega(o.U64)
+    ref0 = o.block_orth(np.asfortranarray(Qi.copy()), i, V.copy(), om)
+    spread = _sensitivity(Qi, V, om, ref0)
+    assert spread is not None   # the accepted size is not on a knife edge
+    p, ref = _check_block(lib, Qi, V, spread=spread)
     assert 1 <= p < s
 
 
