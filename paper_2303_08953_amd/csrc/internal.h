@@ -272,6 +272,17 @@ void col_update(QView<T> Q, int ma, int vcol, const double* w,
                 const double* vscale, const int* pmask, int64_t nrows,
                 double* R, double* Rinv, int* p_out, Partials& P,
                 hipStream_t st);
+// The first CGS update of a one-column block fused with the second
+// projection: v' = v - Q(:, 0:ma) w (as col_update without vscale/pmask),
+// Alg. 3 on g = v'^T v' (p_out, R, Rinv as col_update), and
+// C(0:ma) = Q(:, 0:ma)^T v' / R[0] (zero when *p_out = 0), i.e. what
+// col_dots(Q, ma, vcol, p_out, Rinv, ...) gives after col_update, from one
+// pass over Q(:, 0:ma).  Returns false, enqueueing nothing, when ma is
+// outside [1, 32]; the caller then takes the two separate passes.
+template <typename T>
+bool col_update_dots(QView<T> Q, int ma, int vcol, const double* w,
+                     int64_t nrows, double* R, double* Rinv, int* p_out,
+                     double* C, Partials& P, hipStream_t st);
 // v *= *z when *pmask > 0.
 template <typename T>
 void col_scale(QView<T> Q, int vcol, const double* z, const int* pmask,

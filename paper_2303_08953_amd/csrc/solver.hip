@@ -205,9 +205,14 @@ void orth_block(QView<T> Q, int64_t nrows, int nb, int s, double omega,
     // second projection is taken as (Q^T v) / r1 and the second update
     // scales v on the way.  With a scalar r1 this changes only the rounding.
     col_dots<T>(Qc, nb, nb, nullptr, nullptr, nrows, w.W, w.P, st);
-    col_update<T>(Q, nb, nb, w.W, nullptr, nullptr, nrows, w.Z, w.Zinv, p1,
-                  w.P, st);
-    col_dots<T>(Qc, nb, nb, p1, w.Zinv, nrows, w.R2, w.P, st);
+    // up to 32 prior columns the first update and the second projection
+    // share one pass over Q (the columns stay in registers in between)
+    if (!col_update_dots<T>(Q, nb, nb, w.W, nrows, w.Z, w.Zinv, p1, w.R2,
+                            w.P, st)) {
+      col_update<T>(Q, nb, nb, w.W, nullptr, nullptr, nrows, w.Z, w.Zinv, p1,
+                    w.P, st);
+      col_dots<T>(Qc, nb, nb, p1, w.Zinv, nrows, w.R2, w.P, st);
+    }
     col_update<T>(Q, nb, nb, w.R2, w.Zinv, p1, nrows, w.Zt, w.Ztinv, p2, w.P,
                   st);
     col_scale<T>(Q, nb, w.Ztinv, p2, nrows, st);

@@ -1188,6 +1188,65 @@ __global__ __launch_bounds__(kBlock) void k_col_update(
   }
 }
 
+// The first CGS pass of a one-column block with the second pass's
+// projection in the same sweep: v' = Q(:, vcol) -= Q(:, 0:ma) w (w float64,
+// rounded to T and subtracted in the same column order as in
+// k_col_update), and per chunk
+// part[chunk][0:ma] = sum over the chunk's rows of Q(r, c) v'(r) and
+// part[chunk][ma] = sum of v'(r)^2.  The MA <= 32 columns of a row stay in
+// registers between the update and the dot products, so Q(:, 0:ma) is read
+// once for both; absent columns (ma < MA) load column 0 and get weight 0,
+// their dot products are not stored.
+template <typename T, int MA>
+__global__ __launch_bounds__(kBlock) void k_col_update_dots(
+    QView<T> Q, int ma, int vcol, const double* __restrict__ w,
+    int64_t npanels, int chunks, double* __restrict__ part) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int chunk = blockIdx.x;
+  const int64_t p0 = npanels * chunk / chunks;
+  const int64_t p1 = npanels * (chunk + 1) / chunks;
+  T wt[MA];
+  int64_t oc[MA];
+#pragma unroll
+  for (int j = 0; j < MA; ++j) {
+    wt[j] = j < ma ? (T)w[j] : (T)0;
+    oc[j] = (int64_t)(j < ma ? j : 0) * Q.cstride;
+  }
+  T acc[MA];
+#pragma unroll
+  for (int j = 0; j < MA; ++j) acc[j] = (T)0;
+  double ss = 0.0;
+  for (int64_t pp = p0 + wave; pp < p1; pp += kBlock / kWave) {
+    T* rb = Q.base + Q.row_off(pp * kPanel) + lane;
+    T v = rb[(int64_t)vcol * Q.cstride];
+    T q[MA];
+#pragma unroll
+    for (int j = 0; j < MA; ++j) q[j] = rb[oc[j]];
+#pragma unroll
+    for (int j = 0; j < MA; ++j) v -= q[j] * wt[j];
+    rb[(int64_t)vcol * Q.cstride] = v;
+    ss += (double)v * (double)v;
+#pragma unroll
+    for (int j = 0; j < MA; ++j) acc[j] += q[j] * v;
+  }
+  __shared__ double red[kBlock / kWave][MA + 1];
+#pragma unroll
+  for (int j = 0; j <= MA; ++j) {
+    double t = j < MA ? (double)acc[j] : ss;
+    for (int off = kWave / 2; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (lane == 0) red[wave][j] = t;
+  }
+  __syncthreads();
+  const int e = threadIdx.x;
+  if (e <= ma) {
+    const int src = e < ma ? e : MA;
+    double t = red[0][src];
+    for (int k = 1; k < kBlock / kWave; ++k) t += red[k][src];
+    part[(int64_t)chunk * (ma + 1) + e] = t;
+  }
+}
+
 // Fixed-order sum over the chunks of ne = ndots + norm partials (ndots dot
 // products, then with norm the square sum g).  Sixteen wavefronts split the
 // chunks, lane = output, as in k_reduce_chunks.  live = (pmask == NULL or
@@ -1198,13 +1257,19 @@ __global__ __launch_bounds__(kBlock) void k_col_update(
 //   finite, else *p_out = 0 and R, Rinv untouched.
 // - dots_out[0:ndots] = the dots times *dscale (when given), zero when not
 //   live.
+// - With norm_scales (needs norm and ndots <= 64): the dots are scaled by
+//   the 1 / R[0] just computed instead, and are zero when *p_out = 0 (the
+//   second CGS projection of the normalised vector, from the sums of the
+//   unnormalised one).
 __global__ __launch_bounds__(kRedWaves * kWave) void k_col_finish(
     const double* __restrict__ part, int64_t nchunks, int ndots, int norm,
     const int* __restrict__ pmask, const double* __restrict__ dscale,
     double* __restrict__ dots_out, double* __restrict__ R,
-    double* __restrict__ Rinv, int* p_out) {
+    double* __restrict__ Rinv, int* p_out, int norm_scales) {
   __shared__ double red[kRedWaves][kWave];
-  __shared__ double gsum;
+  __shared__ double sums[kWave];
+  __shared__ double gsum, gscale;
+  __shared__ int gok;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int ne = ndots + norm;
   const bool live = pmask == nullptr || *pmask > 0;
@@ -1229,7 +1294,10 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_col_finish(
       double t = 0.0;
       for (int q = 0; q < kRedWaves; ++q) t += red[q][lane];
       if (e < ndots) {
-        if (dots_out) dots_out[e] = live ? t * sc : 0.0;
+        if (norm_scales)
+          sums[e] = t;
+        else if (dots_out)
+          dots_out[e] = live ? t * sc : 0.0;
       } else {
         gsum = t;
       }
@@ -1245,6 +1313,13 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_col_finish(
       Rinv[0] = 1.0 / r;
     }
     *p_out = ok ? 1 : 0;
+    gok = ok ? 1 : 0;
+    gscale = ok ? 1.0 / sqrt(g) : 0.0;
+  }
+  if (norm_scales) {
+    __syncthreads();
+    const int e = threadIdx.x;
+    if (e < ndots) dots_out[e] = gok ? sums[e] * gscale : 0.0;
   }
 }
 
@@ -1657,6 +1732,7 @@ int col_chunks(int64_t npanels, int ctiles, int64_t per_chunk,
   return (int)c;
 }
 constexpr int kColTile = 16;
+constexpr int kColFused = 32;  // widest fused update + re-projection
 }  // namespace
 
 template <typename T>
@@ -1690,7 +1766,7 @@ void col_dots(QView<const T> Q, int ma, int vcol, const int* pmask,
   hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(kRedWaves * kWave), 0, st,
                      (const double*)P.buf, (int64_t)chunks, ma, 0, pmask,
                      dscale, C, (double*)nullptr, (double*)nullptr,
-                     (int*)nullptr);
+                     (int*)nullptr, 0);
   SGM_CHECK_LAUNCH();
 }
 
@@ -1708,8 +1784,36 @@ void col_update(QView<T> Q, int ma, int vcol, const double* w,
   hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(kRedWaves * kWave), 0, st,
                      (const double*)P.buf, (int64_t)chunks, 0, 1, pmask,
                      (const double*)nullptr, (double*)nullptr, R, Rinv,
-                     p_out);
+                     p_out, 0);
   SGM_CHECK_LAUNCH();
+}
+
+template <typename T>
+bool col_update_dots(QView<T> Q, int ma, int vcol, const double* w,
+                     int64_t nrows, double* R, double* Rinv, int* p_out,
+                     double* C, Partials& P, hipStream_t st) {
+  if (ma < 1 || ma > kColFused) return false;
+  const int64_t npanels = nrows / kPanel;
+  const int chunks = col_chunks(npanels, 1, ma + 1, P);
+#define SGM_CUD(MA)                                                       \
+  hipLaunchKernelGGL((k_col_update_dots<T, MA>), dim3(chunks), dim3(kBlock), \
+                     0, st, Q, ma, vcol, w, npanels, chunks, P.buf)
+  if (ma <= 4)
+    SGM_CUD(4);
+  else if (ma <= 8)
+    SGM_CUD(8);
+  else if (ma <= 16)
+    SGM_CUD(16);
+  else
+    SGM_CUD(32);
+#undef SGM_CUD
+  SGM_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(kRedWaves * kWave), 0, st,
+                     (const double*)P.buf, (int64_t)chunks, ma, 1,
+                     (const int*)nullptr, (const double*)nullptr, C, R, Rinv,
+                     p_out, 1);
+  SGM_CHECK_LAUNCH();
+  return true;
 }
 
 template <typename T>
@@ -1743,6 +1847,9 @@ void col_scale(QView<T> Q, int vcol, const double* z, const int* pmask,
                               double*, int*, Partials&, hipStream_t);        \
   template void col_scale<T>(QView<T>, int, const double*, const int*,       \
                              int64_t, hipStream_t);                          \
+  template bool col_update_dots<T>(QView<T>, int, int, const double*,       \
+                                   int64_t, double*, double*, int*, double*, \
+                                   Partials&, hipStream_t);                  \
   template bool trsm_proj<T>(QView<T>, int, int, int, const double*, int,    \
                              const int*, int64_t, double*, int, Partials&,   \
                              hipStream_t);                                   \
