@@ -278,7 +278,7 @@ void col_update(QView<T> Q, int ma, int vcol, const double* w,
 // C(0:ma) = Q(:, 0:ma)^T v' / R[0] (zero when *p_out = 0), i.e. what
 // col_dots(Q, ma, vcol, p_out, Rinv, ...) gives after col_update, from one
 // pass over Q(:, 0:ma).  Returns false, enqueueing nothing, when ma is
-// outside [1, 32]; the caller then takes the two separate passes.
+// outside [1, 256]; the caller then takes the two separate passes.
 template <typename T>
 bool col_update_dots(QView<T> Q, int ma, int vcol, const double* w,
                      int64_t nrows, double* R, double* Rinv, int* p_out,

@@ -205,7 +205,7 @@ void orth_block(QView<T> Q, int64_t nrows, int nb, int s, double omega,
     // second projection is taken as (Q^T v) / r1 and the second update
     // scales v on the way.  With a scalar r1 this changes only the rounding.
     col_dots<T>(Qc, nb, nb, nullptr, nullptr, nrows, w.W, w.P, st);
-    // up to 32 prior columns the first update and the second projection
+    // up to 256 prior columns the first update and the second projection
     // share one pass over Q (the columns stay in registers in between)
     if (!col_update_dots<T>(Q, nb, nb, w.W, nrows, w.Z, w.Zinv, p1, w.R2,
                             w.P, st)) {

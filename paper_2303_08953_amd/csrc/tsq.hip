@@ -1247,6 +1247,79 @@ __global__ __launch_bounds__(kBlock) void k_col_update_dots(
   }
 }
 
+// The same pass for 32 < ma <= 256 prior columns: the K = blockDim / 64
+// wavefronts of a workgroup walk the chunk's panels together, wavefront w
+// holding columns [32 w, 32 w + 32) of the panel's rows in registers.
+// Each forms its share of Q w for its rows; the shares meet in LDS and
+// every wavefront subtracts them from v in the same order, so all of them
+// hold the same v'; wavefront 0 stores it and keeps the square sum, and
+// each wavefront accumulates the dot products of its own columns.  Two LDS
+// slots alternate between panels, so one barrier per panel suffices.
+constexpr int kColWave = 32;      // columns per wavefront
+constexpr int kColWideMax = 256;  // 8 wavefronts
+template <typename T>
+__global__ __launch_bounds__(kColWideMax / kColWave * kWave) void
+k_col_update_dots_wide(QView<T> Q, int ma, int vcol,
+                       const double* __restrict__ w, int64_t npanels,
+                       int chunks, double* __restrict__ part) {
+  constexpr int CW = kColWave;
+  constexpr int KMAX = kColWideMax / kColWave;
+  __shared__ T share[2][KMAX][kWave];
+  __shared__ double red[KMAX][CW + 1];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int nwv = blockDim.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  const int chunk = blockIdx.x;
+  const int64_t p0 = npanels * chunk / chunks;
+  const int64_t p1 = npanels * (chunk + 1) / chunks;
+  const int c0 = wave * CW;
+  T wt[CW];
+  int64_t oc[CW];
+#pragma unroll
+  for (int j = 0; j < CW; ++j) {
+    const bool in = c0 + j < ma;
+    wt[j] = in ? (T)w[c0 + j] : (T)0;
+    oc[j] = (int64_t)(in ? c0 + j : 0) * Q.cstride;
+  }
+  T acc[CW];
+#pragma unroll
+  for (int j = 0; j < CW; ++j) acc[j] = (T)0;
+  double ss = 0.0;
+  int slot = 0;
+  for (int64_t pp = p0; pp < p1; ++pp, slot ^= 1) {
+    T* rb = Q.base + Q.row_off(pp * kPanel) + lane;
+    const T v = rb[(int64_t)vcol * Q.cstride];
+    T q[CW];
+#pragma unroll
+    for (int j = 0; j < CW; ++j) q[j] = rb[oc[j]];
+    T y = (T)0;
+#pragma unroll
+    for (int j = 0; j < CW; ++j) y += q[j] * wt[j];
+    share[slot][wave][lane] = y;
+    __syncthreads();
+    T vn = v;
+    for (int k = 0; k < nwv; ++k) vn -= share[slot][k][lane];
+    if (wave == 0) {
+      rb[(int64_t)vcol * Q.cstride] = vn;
+      ss += (double)vn * (double)vn;
+    }
+#pragma unroll
+    for (int j = 0; j < CW; ++j) acc[j] += q[j] * vn;
+  }
+#pragma unroll
+  for (int j = 0; j <= CW; ++j) {
+    double t = j < CW ? (double)acc[j] : ss;
+    for (int off = kWave / 2; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (lane == 0) red[wave][j] = t;
+  }
+  __syncthreads();
+  // dots of column c from its wavefront's row, the square sum from wave 0
+  for (int e = threadIdx.x; e <= ma; e += blockDim.x) {
+    const double t = e < ma ? red[e / CW][e % CW] : red[0][CW];
+    part[(int64_t)chunk * (ma + 1) + e] = t;
+  }
+}
+
 // Fixed-order sum over the chunks of ne = ndots + norm partials (ndots dot
 // products, then with norm the square sum g).  Sixteen wavefronts split the
 // chunks, lane = output, as in k_reduce_chunks.  live = (pmask == NULL or
@@ -1257,7 +1330,7 @@ __global__ __launch_bounds__(kBlock) void k_col_update_dots(
 //   finite, else *p_out = 0 and R, Rinv untouched.
 // - dots_out[0:ndots] = the dots times *dscale (when given), zero when not
 //   live.
-// - With norm_scales (needs norm and ndots <= 64): the dots are scaled by
+// - With norm_scales (needs norm and ndots <= 256): the dots are scaled by
 //   the 1 / R[0] just computed instead, and are zero when *p_out = 0 (the
 //   second CGS projection of the normalised vector, from the sums of the
 //   unnormalised one).
@@ -1267,7 +1340,7 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_col_finish(
     double* __restrict__ dots_out, double* __restrict__ R,
     double* __restrict__ Rinv, int* p_out, int norm_scales) {
   __shared__ double red[kRedWaves][kWave];
-  __shared__ double sums[kWave];
+  __shared__ double sums[kColWideMax];
   __shared__ double gsum, gscale;
   __shared__ int gok;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
@@ -1318,8 +1391,8 @@ __global__ __launch_bounds__(kRedWaves * kWave) void k_col_finish(
   }
   if (norm_scales) {
     __syncthreads();
-    const int e = threadIdx.x;
-    if (e < ndots) dots_out[e] = gok ? sums[e] * gscale : 0.0;
+    for (int e = threadIdx.x; e < ndots; e += blockDim.x)
+      dots_out[e] = gok ? sums[e] * gscale : 0.0;
   }
 }
 
@@ -1732,7 +1805,7 @@ int col_chunks(int64_t npanels, int ctiles, int64_t per_chunk,
   return (int)c;
 }
 constexpr int kColTile = 16;
-constexpr int kColFused = 32;  // widest fused update + re-projection
+constexpr int kColFused = 32;  // widest one-wavefront fused pass
 }  // namespace
 
 template <typename T>
@@ -1792,9 +1865,15 @@ template <typename T>
 bool col_update_dots(QView<T> Q, int ma, int vcol, const double* w,
                      int64_t nrows, double* R, double* Rinv, int* p_out,
                      double* C, Partials& P, hipStream_t st) {
-  if (ma < 1 || ma > kColFused) return false;
+  if (ma < 1 || ma > kColWideMax) return false;
   const int64_t npanels = nrows / kPanel;
   const int chunks = col_chunks(npanels, 1, ma + 1, P);
+  if (ma > kColFused) {
+    const int nwv = (ma + kColWave - 1) / kColWave;
+    hipLaunchKernelGGL(k_col_update_dots_wide<T>, dim3(chunks),
+                       dim3(nwv * kWave), 0, st, Q, ma, vcol, w, npanels,
+                       chunks, P.buf);
+  } else {
 #define SGM_CUD(MA)                                                       \
   hipLaunchKernelGGL((k_col_update_dots<T, MA>), dim3(chunks), dim3(kBlock), \
                      0, st, Q, ma, vcol, w, npanels, chunks, P.buf)
@@ -1807,6 +1886,7 @@ bool col_update_dots(QView<T> Q, int ma, int vcol, const double* w,
   else
     SGM_CUD(32);
 #undef SGM_CUD
+  }
   SGM_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(kRedWaves * kWave), 0, st,
                      (const double*)P.buf, (int64_t)chunks, ma, 1,

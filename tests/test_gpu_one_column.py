@@ -2,11 +2,13 @@
 with the 1 x 1 partial Cholesky of Alg. 3) against the oracle's
 block_orth, in float64 and float32.
 
-Up to 32 prior columns the first update and the second projection share
-one pass over Q (4-, 8-, 16- and 32-column register tiles); beyond that
-they are two passes.  The cases reach every tile width and the two-pass
-path, on a ragged row count, and include a vector almost inside span(Q),
-where the second projection carries the re-orthogonalisation.
+Up to 256 prior columns the first update and the second projection share
+one pass over Q: one wavefront per panel with 4-, 8-, 16- and 32-column
+register tiles up to 32 columns, then 2 to 8 wavefronts per panel with 32
+columns each; beyond 256 they are two passes.  The cases reach every tile
+width, every wavefront count's edges and the two-pass path, on a ragged
+row count, and include a vector almost inside span(Q), where the second
+projection carries the re-orthogonalisation.
 """
 import numpy as np
 import pytest
@@ -49,7 +51,19 @@ def _run(lib, Qi, v, precision):
     return p, Rt, Rk, cols_of(Qd, n, ld, i + 1).astype(np.float64), ref
 
 
-@pytest.mark.parametrize("i", [3, 8, 12, 20, 32, 33, 47])
+@pytest.mark.parametrize("i", [1, 33, 64, 65, 129, 200, 256, 257])
+def test_one_column_fp64(lib, i):
+    n = 9001
+    Qi, v = _block(n, i, seed=600 + i)
+    p, Rt, Rk, Qg, ref = _run(lib, Qi, v, "fp64")
+    assert p == ref.p == 1
+    assert np.abs(Qg[:, i] - ref.Qk[:, 0]).max() <= 1e-12
+    assert np.abs(Rt[:, 0] - ref.R_top[:, 0]).max() <= 1e-12 * np.abs(ref.R_top).max()
+    assert abs(Rk[0, 0] - ref.R_kk[0, 0]) <= 1e-12 * abs(ref.R_kk[0, 0])
+    assert o.loo(Qg[:, :i + 1]) <= 1e-13
+
+
+@pytest.mark.parametrize("i", [3, 8, 12, 20, 32, 33, 47, 100, 256, 257])
 def test_one_column_fp32(lib, i):
     n = 9001
     Qi, v = _block(n, i, seed=500 + i)
@@ -65,7 +79,8 @@ def test_one_column_fp32(lib, i):
 
 @pytest.mark.parametrize("precision,i,tol_loo",
                          [("fp64", 32, 1e-13), ("fp64", 40, 1e-13),
-                          ("fp32_ir", 32, 1e-5)])
+                          ("fp64", 200, 1e-13), ("fp32_ir", 32, 1e-5),
+                          ("fp32_ir", 100, 1e-5)])
 def test_one_column_near_span(lib, precision, i, tol_loo):
     """v = Q c + 1e-6 N in float64 (1e-3 N in float32): the first pass
     leaves components along Q of about u / delta relative to the result,
