@@ -309,6 +309,47 @@ def test_solve_jacobi_variable_coefficients(lib):
     assert rel <= 1e-8
 
 
+def test_update_values_refreshes_every_copy(lib):
+    """sgm_matrix_update_values on the same pattern reaches every derived
+    copy: the FP64 and FP32 SELL values, the transposed copy and the
+    diagonal behind Jacobi scaling (a solve with the new values matches the
+    oracle on the new matrix)."""
+    import torch
+    A0 = W.var_conv_diff_3d(14, seed=3)
+    A1 = W.var_conv_diff_3d(14, seed=5)
+    assert np.array_equal(A0.row_ptr, A1.row_ptr)
+    assert np.array_equal(A0.col, A1.col)
+    assert not np.allclose(A0.val, A1.val)
+    G = lib.Matrix.from_csr(A0)
+    G.update_values(torch.tensor(A1.val, device="cuda"))
+    M = csr(A1)
+    x = np.random.default_rng(1).standard_normal(A1.n)
+    scale = np.abs(M) @ np.abs(x)
+    y = G.spmv(x).cpu().numpy()
+    assert np.all(np.abs(y - M @ x) <= 4 * 2.0 ** -52 * 8 * scale)
+    yt = G.spmv(x, transpose=True).cpu().numpy()
+    assert np.all(np.abs(yt - M.T @ x) <= 4 * 2.0 ** -52 * 8 *
+                  (np.abs(M.T) @ np.abs(x)))
+    x32 = x.astype(np.float32)
+    y32 = G.spmv(torch.tensor(x32, device="cuda"),
+                 precision="fp32_ir").cpu().numpy()
+    assert np.all(np.abs(y32 - M.astype(np.float32) @ x32)
+                  <= 4 * 2.0 ** -23 * 8 * scale)
+    b = W.rhs(A1.n, 3)
+    opts = dict(s_max=16, restart=64, tol=1e-10, precond="jacobi")
+    ref = o.solve(M, b, None, o.Options(max_restarts=400, **opts))
+    gpu = lib.solve(G, b, max_restarts=400, **opts)
+    xg = gpu.x.cpu().numpy()
+    assert gpu.status == lib.OK and ref.status == "ok"
+    assert list(gpu.s_hist) == ref.s_hist
+    assert np.linalg.norm(xg - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
+    g32 = lib.solve(G, b, max_restarts=400, precision="fp32_ir",
+                    inner_tol=1e-6, max_outer=100, **opts)
+    assert g32.status == lib.OK
+    assert (np.linalg.norm(b - M @ g32.x.cpu().numpy())
+            <= 1.0001e-10 * np.linalg.norm(b))
+
+
 @pytest.mark.parametrize("n,band,ibytes", [(70001, 40000, 2),
                                             (140001, 70000, 4)])
 def test_solve_wide_band_columns(lib, n, band, ibytes):
