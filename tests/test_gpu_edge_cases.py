@@ -155,3 +155,23 @@ def test_converges_inside_queued_prephase(lib, shift):
     x = r.x.cpu().numpy()
     assert np.linalg.norm(x - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
     assert np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("cap", [0, 5])
+def test_short_history_buffers(lib, cap):
+    """History buffers shorter than the histories: sgm_solve writes the
+    first cap entries and reports the full lengths in info (n_hist,
+    n_blocks); the solution is unaffected."""
+    A = W.conv_diff_2d(64, 10.0)
+    b = W.rhs(A.n, 1)
+    G = lib.Matrix.from_csr(A)
+    full = lib.solve(G, b, s_max=8, restart=64, tol=1e-10)
+    short = lib.solve(G, b, s_max=8, restart=64, tol=1e-10, hist_cap=cap)
+    assert full.info["n_hist"] == len(full.res_hist) > cap
+    assert full.info["n_blocks"] == len(full.s_hist) > cap
+    assert short.info["n_hist"] == full.info["n_hist"]
+    assert short.info["n_blocks"] == full.info["n_blocks"]
+    assert len(short.res_hist) == cap and len(short.s_hist) == cap
+    assert np.array_equal(short.res_hist, full.res_hist[:cap])
+    assert np.array_equal(short.s_hist, full.s_hist[:cap])
+    assert np.array_equal(short.x.cpu().numpy(), full.x.cpu().numpy())
