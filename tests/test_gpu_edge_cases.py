@@ -175,3 +175,26 @@ def test_short_history_buffers(lib, cap):
     assert np.array_equal(short.res_hist, full.res_hist[:cap])
     assert np.array_equal(short.s_hist, full.s_hist[:cap])
     assert np.array_equal(short.x.cpu().numpy(), full.x.cpu().numpy())
+
+
+def test_solve_on_a_side_stream(lib):
+    """All work is enqueued on the caller's stream: a solve under a
+    non-default torch stream, whose right-hand side is produced on that
+    stream just before the call, gives bitwise the default-stream result."""
+    import torch
+    A = W.conv_diff_2d(64, 10.0)
+    b = W.rhs(A.n, 1)
+    G = lib.Matrix.from_csr(A)
+    ref = lib.solve(G, b, s_max=8, restart=64, tol=1e-10)
+    bd = torch.tensor(b, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b2 = bd * 2.0
+        b2.mul_(0.5)
+        r = lib.solve(G, b2, s_max=8, restart=64, tol=1e-10)
+        x = r.x.clone()
+    side.synchronize()
+    assert r.status == lib.OK
+    assert np.array_equal(x.cpu().numpy(), ref.x.cpu().numpy())
+    assert list(r.s_hist) == list(ref.s_hist)
