@@ -538,6 +538,10 @@ def main():
         "algorithmic_bytes_per_launch": int(alg_bytes),
         "avg_launch_us": round(avg_ms * 1e3, 2), "launches": int(n_spmv),
         "spmv_source_sha256_16": khash}
+    if primary == "fp64" and "fp32_ir" in infos:
+        # the same figure for the float32 inner solves' SpMV
+        out["roofline_fp32"] = spmv_roofline(A, G, infos["fp32_ir"], 4,
+                                             "float")
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on one restart cycle (CPU)")
         out["cpu_baseline"] = cpu_baseline(
