@@ -123,8 +123,8 @@ def _basis_and_block(A, i, s, seed=2, basis="scaled_newton"):
 # first update + second projection at each of its widths, i = 33 the two
 # separate passes
 @pytest.mark.parametrize("i,s", [(1, 1), (5, 1), (9, 1), (17, 1), (32, 1),
-                                 (33, 1), (1, 8), (9, 8), (33, 16), (70, 32),
-                                 (97, 32)])
+                                 (33, 1), (1, 8), (1, 32), (9, 8), (17, 32),
+                                 (33, 16), (70, 32), (97, 32)])
 def test_block_orth_matches_oracle(lib, i, s):
     import torch
     A = W.conv_diff_2d(64, 10.0)
