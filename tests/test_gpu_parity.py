@@ -185,11 +185,17 @@ def test_shifts_match_oracle_on_arnoldi_hessenberg(lib):
     assert s0 == s0r
 
 
-@pytest.mark.parametrize("lmax,expect", [(200.0, 134), (2000.0, 17)])
-def test_estimator_on_gpu_matches_oracle_and_paper(lib, lmax, expect):
+@pytest.mark.parametrize("lmax,case", [(200.0, "uniform_200"),
+                                       (2000.0, "max_2000")])
+def test_estimator_on_gpu_matches_oracle(lib, lmax, case):
     """Sec. 4.4 Test 8 through the GPU path (Francis QR on a 200 x 200
-    Hessenberg held in global memory, Leja, estimator): same s0* as the
-    oracle, within +-3 of the paper's value."""
+    Hessenberg held in global memory, Leja, estimator): the same s0* as
+    the oracle, which is the oracle's adopted reading of Eq.
+    (auxiliarymatrix) (137 and 16; the paper prints 134 and 17, which no
+    reading reproduces).  Both column norms sit at least 0.25 decades
+    from Omega_est, so rounding differences in the Ritz values cannot
+    move s0*: the comparison is exact."""
+    from test_oracle_pins import E8_ADOPTED
     lam = np.arange(1.0, 201.0)
     lam[-1] = lmax
     Ad = sp.diags(lam).tocsr()
@@ -200,9 +206,9 @@ def test_estimator_on_gpu_matches_oracle_and_paper(lib, lmax, expect):
     H = r.trace["H_first_cycle"][:200, :200].copy()
     ritz, rec, s0, hits = lib.shifts(H, 200, omega_est=1e7)
     sh = o.newton_shifts(o.leja_order(np.linalg.eigvals(H)), scaled=True)
-    s0r, _ = o.estimator(sh.ritz, sh.gamma, o.U64, 1e7)
-    assert abs(s0 - s0r) <= 1
-    assert abs(s0 - expect) <= 3
+    s0r, lg = o.estimator(sh.ritz, sh.gamma, o.U64, 1e7)
+    assert min(abs(lg[s0r - 1] - 7.0), abs(lg[s0r] - 7.0)) >= 0.25
+    assert s0 == s0r == E8_ADOPTED[case]
     assert np.abs(np.sort(ritz.real) - lam).max() <= 1e-8 * lmax
 
 

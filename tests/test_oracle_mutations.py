@@ -110,6 +110,19 @@ CASES = [
      "G2 = (Qk.T @ Qk).astype(np.float64) - R2d.T @ R2d",
      "G2 = (Qk.T @ Qk).astype(np.float64) - 0.0 * (R2d.T @ R2d)",
      [(P.test_pythagorean_second_pass_block, (1e-12,))]),
+    ("fp32_model_with_fp64_roundoff",
+     "self.u = U32 if self.wd == np.float32 else U64",
+     "self.u = U64",
+     [(P.test_fp32_partial_cholqr_stops_at_single_precision_bound, ()),
+      (P.test_fp32_estimator_tracks_single_precision_basis_growth, ())]),
+    ("fp32_block_bound_from_fp64",
+     "self.omega = opts.omega if opts.omega > 0 else default_omega(self.u)",
+     "self.omega = opts.omega if opts.omega > 0 else default_omega(U64)",
+     [(P.test_fp32_partial_cholqr_stops_at_single_precision_bound, ())]),
+    ("fp32_model_runs_in_fp64",
+     "self.wd = np.dtype(opts.work_dtype)",
+     "self.wd = np.dtype(np.float64)",
+     [(P.test_fp32_inner_cycle_is_the_gmres_minimiser, ())]),
     ("givens_rhs_not_rotated",
      "self.g[col + 1] = -ss * gc",
      "self.g[col + 1] = ss * gc",

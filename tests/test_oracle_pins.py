@@ -172,7 +172,11 @@ def test_E1_monomial_step_size_six():
         r = o.solve(csr(A), b, opts=o.Options(
             s_max=10, restart=100, max_restarts=0, tol=1e-300,
             basis="monomial", omega=1e7, record=True))
-        full = [p for (_, i, se, _, p) in r.blocks if se == 10]
+        # every block that the end of the cycle does not cut short keeps
+        # s = 6: the first (s_eff = 10) and the ones after it (s_eff = 6,
+        # since s never grows inside a cycle)
+        full = [p for (_, i, se, _, p) in r.blocks if se >= g["adapted_s"]]
+        assert len(full) >= 15
         assert all(p == g["adapted_s"] for p in full)
         kice = r.trace["first_block"]["kappas"]
         r2 = o.solve(csr(A), b, opts=o.Options(
@@ -234,13 +238,28 @@ def _ritz_from_arnoldi(lam, seed):
     return np.linalg.eigvals(H[:k, :k])
 
 
+# The oracle's s0* on the two Test 8 spectra.  The paper prints 134 and 17
+# (Sec. 4.4).  Eq. (auxiliarymatrix) taken as printed gives 137 and 16, and
+# so do the alternative readings tried (epsilon only above the diagonal,
+# epsilon = 2^-52 or 1e-16, the 1-, 2- or max-norm of column j, the norm
+# relative to column 1, argmax over all j, Omega_est = 1e7 or
+# 0.1 u^{-1/2}, every Leja tie rule): none gives both printed values, and
+# the value 134 is not reached for any epsilon with this spectrum.  The
+# paper's Ritz values came from its own Arnoldi run, which it does not
+# give.  So this is "parity unpinned" against the paper; the adopted
+# (literal) values are asserted exactly, here and on the GPU.
+E8_ADOPTED = {"uniform_200": 137, "max_2000": 16}
+
+
 def test_E8_estimator_prediction():
     """P7d, Test 8 (Sec. 4.4): diagonal N = 200, eigenvalues 1..200 (and the
-    same with the largest raised to 2000).  The paper reports s0* = 134 and
-    17 with Omega_est = 1e7, and kappa(V_1:j) reaching 1e8 at j = 15 for the
-    second matrix.  The literal reading of Eq. (auxiliarymatrix) gives 137
-    and 16 here; the pin accepts +-3 (Ritz values and start vectors of the
-    paper's run are not given)."""
+    same with the largest raised to 2000), Omega_est = 1e7.  The estimator
+    is unpinned against the paper's printed s0* (see E8_ADOPTED); what is
+    pinned here is the rest of the experiment: Ritz values from an Arnoldi
+    run equal the eigenvalues, s0* does not depend on which of them the
+    run returns first, and the float64 scaled Newton basis' condition
+    number crosses 1e8 where the paper says (j = 15 for the second
+    matrix, within the spread of random start vectors)."""
     g = golden("paper_stability_results.json")["E8"]
     for case in ("uniform_200", "max_2000"):
         lam = np.arange(1.0, 201.0)
@@ -250,7 +269,11 @@ def test_E8_estimator_prediction():
         assert np.abs(np.sort(ritz.real) - lam).max() <= 1e-8 * lam.max()
         sh = o.newton_shifts(o.leja_order(ritz), scaled=True)
         s0, _ = o.estimator(sh.ritz, sh.gamma, o.U64, 1e7)
-        assert abs(s0 - g[case]["s0_star"]) <= 3, (case, s0)
+        assert s0 == E8_ADOPTED[case], (case, s0)
+        # the same from the exact eigenvalues in reversed input order
+        sx = o.newton_shifts(o.leja_order(lam[::-1].astype(complex)),
+                             scaled=True)
+        assert o.estimator(sx.ritz, sx.gamma, o.U64, 1e7)[0] == s0
         if case == "max_2000":
             v = np.random.default_rng(12).standard_normal(200)
             v /= np.linalg.norm(v)
@@ -492,6 +515,109 @@ def test_fp32_inner_refinement_reaches_fp64_accuracy():
     _, _, r32 = _conv_diff_run(work_dtype=np.float32, max_restarts=0,
                                tol=1e-300)
     assert o.loo(r32.trace["Q_first_cycle"]) <= 1e-5
+
+
+
+def _float32_scaled_newton_kappa_crossing(lam, sh, bound, seeds):
+    """First j at which a scaled Newton basis built in float32 arithmetic
+    (numpy, outside the oracle's engine) has kappa(V_1:j) > bound, for
+    each random start vector."""
+    out = []
+    L32 = lam.astype(np.float32)
+    for seed in seeds:
+        v = np.random.default_rng(seed).standard_normal(lam.size)
+        v = (v / np.linalg.norm(v)).astype(np.float32)
+        V = [v]
+        for j in range(lam.size - 1):
+            th, ga, _ = sh.record(j)
+            V.append((L32 * V[-1] - np.float32(th) * V[-1]) / np.float32(ga))
+        Vd = np.array(V, dtype=np.float64).T
+        out.append(next(j for j in range(1, lam.size + 1)
+                        if np.linalg.cond(Vd[:, :j]) > bound))
+    return out
+
+
+def test_fp32_partial_cholqr_stops_at_single_precision_bound():
+    """The float32 inner model's partial CholQR (Alg. 3) uses the bound
+    Omega = 0.1 u^{-1/2} of float32 (Sec. 3.2: Omega ~ 0.1 eps^{-1/2}),
+    409.6.  A monomial Krylov block of Test 1's diagonal matrix, formed in
+    float32, is cut before the first column at which the condition number
+    of the projected block (SVD of a float64 copy, outside the oracle)
+    exceeds 409.6, with the SVD and with the ICE condition estimate.  The
+    same block in float64 keeps Test 1's six columns."""
+    lam = np.linspace(0.1, 10.0, 2000)
+    A = sp.diags(lam).tocsr()
+    bound = 0.1 * 2.0 ** 12
+    for seed in (1, 2):
+        b = W.rhs(lam.size, seed)
+        v = b / np.linalg.norm(b)
+        K = [v]
+        for _ in range(12):
+            K.append(lam * K[-1])
+        V = np.array(K[1:]).T
+        for _ in range(2):
+            V = V - np.outer(v, v @ V)
+        kap = [np.linalg.cond(V[:, :j]) for j in range(1, 13)]
+        expect = next(j for j in range(12) if kap[j] > bound)
+        # away from the bound on both sides: float32 rounding cannot move it
+        assert kap[expect - 1] < 0.5 * bound and kap[expect] > 2 * bound
+        for cond in ("svd", "ice"):
+            r = o.solve(A, b, opts=o.Options(
+                s_max=12, restart=12, max_restarts=0, tol=1e-300,
+                basis="monomial", work_dtype=np.float32, cond=cond,
+                record=True))
+            fb = r.trace["first_block"]
+            assert fb["p1"] == expect and fb["p"] == expect, (cond, fb)
+        r64 = o.solve(A, b, opts=o.Options(
+            s_max=12, restart=12, max_restarts=0, tol=1e-300,
+            basis="monomial", record=True))
+        assert r64.trace["first_block"]["p"] == 6
+
+
+def test_fp32_estimator_tracks_single_precision_basis_growth():
+    """The float32 inner model's initial step size (Sec. 3.5 with the
+    float32 unit round-off and Omega_est = 0.1 u^{-1/2} = 409.6) on Test 8's
+    spectra, given the exact eigenvalues as shifts.  In the paper's own
+    Test 8 the predicted s0* lies within a factor 2.2 of the column at
+    which kappa(V_1:j) crosses the bound (134 vs 62, 17 vs 15).  Here the
+    float32 scaled Newton basis (built with numpy in float32) crosses 409.6
+    at the columns returned by _float32_scaled_newton_kappa_crossing, and
+    s0* must lie within a factor 3 of the earliest of them; the first block
+    then runs at s0* and partial CholQR keeps all of it."""
+    for lmax in (200.0, 2000.0):
+        lam = np.arange(1.0, 201.0)
+        lam[-1] = lmax
+        sh = o.newton_shifts(o.leja_order(lam.astype(complex)), scaled=True)
+        cross = _float32_scaled_newton_kappa_crossing(
+            lam, sh, 0.1 * 2.0 ** 12, seeds=(11, 12, 13))
+        b = np.random.default_rng(11).standard_normal(lam.size)
+        r = o.solve(sp.diags(lam).tocsr(), b, opts=o.Options(
+            s_max=200, restart=200, max_restarts=0, tol=1e-300,
+            work_dtype=np.float32, shifts=lam.astype(complex), record=True))
+        assert 1 <= r.s0_est <= 3 * min(cross), (lmax, r.s0_est, cross)
+        fb = r.trace["first_block"]
+        assert fb["s_eff"] == r.s0_est and fb["p"] == fb["s_eff"]
+
+
+def test_fp32_inner_cycle_is_the_gmres_minimiser():
+    """One float32 inner cycle (the model of Alg. 4 in single precision)
+    returns the GMRES iterate of its Krylov space to O(kappa u32): compared
+    with the dense float64 minimiser after the same number of iterations,
+    the difference is at most 100 kappa(A) 2^-24 and at least 2^-40
+    relative (float32 rounding is really there)."""
+    A = W.conv_diff_2d(16, 10.0)
+    M = csr(A)
+    Ad = A.to_dense()
+    b = W.rhs(A.n, 3)
+    kap = np.linalg.cond(Ad)
+    for k in (8, 16, 24):
+        r = o.solve(M, b, opts=o.Options(
+            s_max=8, restart=k, max_restarts=0, tol=1e-300,
+            work_dtype=np.float32))
+        assert r.iters == k
+        xk = o.gmres_iterates_dense(Ad, b, np.zeros(A.n), k)
+        rel = np.linalg.norm(r.x - xk) / np.linalg.norm(xk)
+        assert 2.0 ** -40 <= rel <= 100 * kap * 2.0 ** -24, (k, rel, kap)
 
 
 # ---------------------------------------------------------------- adjoint
