@@ -784,6 +784,9 @@ class IRResult:
     iters: int
     rel_res_true: float
     res_true_hist: list
+    # per outer step: (||r|| / ||r0||, inner block sizes, inner Givens
+    # estimates relative to the inner right-hand side r / ||r||)
+    inner: list = field(default_factory=list)
 
 
 def solve_ir(A, b, x0=None, opts: Options | None = None, inner_tol=1e-4,
@@ -813,8 +816,9 @@ def solve_ir(A, b, x0=None, opts: Options | None = None, inner_tol=1e-4,
     r = b - A @ x
     beta0 = float(np.linalg.norm(r))
     hist = [1.0]
+    inner_logs = []
     if beta0 == 0.0:
-        return IRResult(x, "ok", 0, 0, 0.0, hist)
+        return IRResult(x, "ok", 0, 0, 0.0, hist, inner_logs)
     Q = np.zeros((n, inner.restart + 1), dtype=np.float32, order="F")
     st = _State(None, inner.s_max)
     if o.shifts is not None:
@@ -838,8 +842,10 @@ def solve_ir(A, b, x0=None, opts: Options | None = None, inner_tol=1e-4,
         rn = (r / beta)
         d = np.zeros(n)
         rr, bb = rn.copy(), 1.0
+        step_s, step_res = [], []
+        inner_logs.append((rel, step_s, step_res))
         for rs in range(inner_restarts + 1):
-            logs = ([], [], [], None)
+            logs = (step_res, step_s, [], None)
             dx, k, conv = eng.cycle(Q, rr, bb, 1.0, st, logs, rs)
             iters += k
             d += dx
@@ -851,7 +857,7 @@ def solve_ir(A, b, x0=None, opts: Options | None = None, inner_tol=1e-4,
         r = b - A @ x
         hist.append(float(np.linalg.norm(r)) / beta0)
     xo = x / dscale if dscale is not None else x
-    return IRResult(xo, status, outer, iters, rel, hist)
+    return IRResult(xo, status, outer, iters, rel, hist, inner_logs)
 
 
 # ---------------------------------------------------------------------------

@@ -166,6 +166,9 @@ class Matrix:
         self.col = _dev(col, torch.int32)
         self.val = _dev(val, torch.float64)
         self.nnz = int(self.col.numel())
+        # bumped by every update_values: the autograd node compares it with
+        # the version its forward solve ran on
+        self.version = 0
         h = C.c_void_p()
         _check(lib().sgm_matrix_create(self.n, self.nnz, _ptr(self.row_ptr),
                                        _ptr(self.col), _ptr(self.val),
@@ -186,6 +189,7 @@ class Matrix:
         self.val = _dev(val, torch.float64)
         _check(lib().sgm_matrix_update_values(self._h, _ptr(self.val),
                                               _stream(stream)))
+        self.version += 1
 
     def info(self):
         n, nnz, snnz = C.c_int64(), C.c_int64(), C.c_int64()
@@ -375,38 +379,66 @@ def _autograd_function():
 
         Backward solves A^T lambda = dL/dx with the same s-step kernels on
         the transposed SELL structure; grad_b = lambda and
-        grad_vals[k] = -lambda[row(k)] x[col(k)] (one fused kernel)."""
+        grad_vals[k] = -lambda[row(k)] x[col(k)] (one fused kernel).
+
+        The forward keeps a copy of vals and the matrix version it solved
+        with; if the shared Matrix was given other values since (another
+        forward, update_values), backward puts these back before the
+        adjoint solve and the gradient.  A solve that stops short of its
+        tolerance raises SgmError unless allow_not_converged is set."""
 
         @staticmethod
-        def forward(ctx, vals, b, A: Matrix, opts: dict):
-            A.update_values(vals.detach())
+        def forward(ctx, vals, b, A: Matrix, opts: dict, allow, trace):
+            vsave = vals.detach().clone()
+            A.update_values(vsave)
             r = solve(A, b.detach(), **opts)
+            if r.status != OK and not allow:
+                raise SgmError(r.status, "forward solve did not converge "
+                               f"(relative residual {r.info['rel_res_true']:.3e})")
+            if trace is not None:
+                trace.append(("forward", r))
             ctx.A = A
             ctx.opts = opts
-            ctx.fwd_info = r.info
-            ctx.save_for_backward(r.x)
+            ctx.allow = allow
+            ctx.trace = trace
+            ctx.version = A.version
+            ctx.save_for_backward(r.x, vsave)
             return r.x
 
         @staticmethod
         def backward(ctx, gx):
-            (x,) = ctx.saved_tensors
+            x, vsave = ctx.saved_tensors
             A = ctx.A
+            if A.version != ctx.version:
+                A.update_values(vsave)
+                ctx.version = A.version
             o = dict(ctx.opts)
             o["transpose"] = not o.get("transpose", False)
-            lam = solve(A, gx.detach().contiguous(), **o).x
+            r = solve(A, gx.detach().contiguous(), **o)
+            if r.status != OK and not ctx.allow:
+                raise SgmError(r.status, "adjoint solve did not converge "
+                               f"(relative residual {r.info['rel_res_true']:.3e})")
+            if ctx.trace is not None:
+                ctx.trace.append(("adjoint", r))
+            lam = r.x
             gv = grad_vals(A, lam, x) if ctx.needs_input_grad[0] else None
             gb = lam if ctx.needs_input_grad[1] else None
-            return gv, gb, None, None
+            return gv, gb, None, None, None, None
 
     return SStepSolve
 
 
-def sstep_solve(vals, b, A: Matrix, **opts):
-    """Differentiable solve: x = A(vals)^{-1} b (see SStepSolve)."""
+def sstep_solve(vals, b, A: Matrix, allow_not_converged=False, trace=None,
+                **opts):
+    """Differentiable solve: x = A(vals)^{-1} b (see SStepSolve).
+
+    trace: an optional list; the forward and adjoint SolveResults are
+    appended to it as ("forward", r) and ("adjoint", r)."""
     global SStepSolve
     if SStepSolve is None:
         SStepSolve = _autograd_function()
-    return SStepSolve.apply(vals, b, A, opts)
+    return SStepSolve.apply(vals, b, A, opts, bool(allow_not_converged),
+                            trace)
 
 
 SStepSolve = None

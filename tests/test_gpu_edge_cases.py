@@ -115,7 +115,7 @@ def test_largest_block(lib):
     assert ref.s_hist[0] == 256
     assert list(r.s_hist) == ref.s_hist
     x = r.x.cpu().numpy()
-    assert np.linalg.norm(x - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
+    assert np.linalg.norm(x - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
 
 
 @pytest.mark.parametrize("bad", [dict(s_max=0), dict(s_max=257),

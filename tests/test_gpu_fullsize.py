@@ -77,15 +77,46 @@ def spmv_rows_match(A, y, x, rows):
         assert abs(y[r] - ref) <= bound, (r, y[r], ref)
 
 
+def poisson3d_kappa(nx):
+    """2-norm condition number of the 7-point Dirichlet Laplacian on an nx^3
+    interior grid, from its closed-form eigenvalues
+    sum_d 2 (1 - cos(k_d pi / (nx + 1)))."""
+    lo = 2.0 * (1.0 - np.cos(np.pi / (nx + 1)))
+    hi = 2.0 * (1.0 - np.cos(nx * np.pi / (nx + 1)))
+    return hi / lo
+
+
+def oracle_golden(name):
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        name)
+    with np.load(path, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
 def test_poisson128_bench_workload(lib):
-    """3D Poisson 128^3, the benchmark configuration: float64 and float32-IR
-    solves to 1e-10 (true residual on the host), the oracle's first restart
-    cycle block by block, sampled SpMV rows."""
+    """3D Poisson 128^3, the benchmark configuration, against the oracle's
+    whole float64 solve of the same seeded system (752 iterations, stored by
+    tests/golden/make_poisson3d_128_oracle.py, which calls only the oracle):
+    - float64: iterations within +-s_max of the oracle's, block sizes
+      identical, every Givens estimate within 1e-6 relative, x within 1e-8
+      relative on 8192 sampled entries, true residual <= 1e-10 on the host;
+    - float32-IR: true residual <= 1e-10, and x within the bound
+      kappa(A) (r_gpu + r_oracle) of the oracle's x (kappa from the
+      closed-form eigenvalues, 6.7e3);
+    - sampled SpMV rows against the CSR sum."""
+    g = oracle_golden("poisson3d_128_oracle.npz")
     A = W.poisson_3d(128)
     M = csr(A)
     b = W.rhs(A.n, 2)
     G = lib.Matrix.from_csr(A)
     kw = dict(s_max=32, restart=128, tol=1e-10)
+    idx = g["sample_idx"]
+    xs_ref = g["x_samples"]
+
+    def sample_rel(x):
+        return np.linalg.norm(x[idx] - xs_ref) / np.linalg.norm(xs_ref)
+
     gpu = lib.solve(G, b, max_restarts=1000, **kw)
     x = gpu.x.cpu().numpy()
     assert gpu.status == lib.OK
@@ -93,20 +124,26 @@ def test_poisson128_bench_workload(lib):
     assert true <= 1e-10
     assert abs(gpu.info["rel_res_true"] - true) <= 1e-6 * true
     check_cycle_invariants(gpu, 128, 32, 32)
-    # the oracle's first cycle (32 pre-phase steps + blocks of 32)
-    ref = o.solve(M, b, opts=o.Options(max_restarts=0, **kw))
-    assert gpu.info["s0_est"] == ref.s0_est
-    assert list(gpu.s_hist[:len(ref.s_hist)]) == ref.s_hist
-    h = np.asarray(gpu.res_hist[:len(ref.res_hist)])
-    hr = np.asarray(ref.res_hist)
-    assert np.all(np.abs(h - hr) <= 1e-6 * hr)
+    assert abs(gpu.info["iters"] - int(g["iters"])) <= 32
+    assert gpu.info["s0_est"] == int(g["s0_est"])
+    assert list(gpu.s_hist) == g["s_hist"].tolist()
+    h, hr = np.asarray(gpu.res_hist), g["res_hist"]
+    assert h.shape == hr.shape and np.all(np.abs(h - hr) <= 1e-6 * hr)
+    err64 = sample_rel(x)
+    assert err64 <= 1e-8, err64
+    assert abs(np.linalg.norm(x) - float(g["x_norm"])) <= 1e-8 * float(g["x_norm"])
     # float32 inner cycles, float64 refinement: same final tolerance
     g32 = lib.solve(G, b, precision="fp32_ir", inner_tol=1e-6, max_outer=500,
                     max_restarts=1000, **kw)
     x32 = g32.x.cpu().numpy()
     assert g32.status == lib.OK
-    assert np.linalg.norm(b - M @ x32) / np.linalg.norm(b) <= 1e-10
-    assert rel(x32, x) <= 1e-6     # kappa(A) ~ 7e3 times 2e-10
+    true32 = np.linalg.norm(b - M @ x32) / np.linalg.norm(b)
+    assert true32 <= 1e-10
+    err32 = sample_rel(x32)
+    bound = poisson3d_kappa(128) * (true32 + float(g["rel_res_true"]))
+    assert err32 <= bound, (err32, bound)
+    print(f"poisson3d_128: error vs oracle fp64 {err64:.2e}, fp32_ir "
+          f"{err32:.2e} (bound {bound:.1e})")
     # SpMV: sampled rows against the CSR sum
     rng = np.random.default_rng(20)
     xr = rng.standard_normal(A.n)
@@ -139,17 +176,21 @@ def test_varcd192_jacobi_first_cycle(lib):
 
 def test_banded_1m_adjoint(lib):
     """Random banded nonsymmetric matrix, n = 1M, 27 nonzeros per row:
-    forward and adjoint float64 solves through the differentiable solve.
+    forward and adjoint float64 solves through the differentiable solve,
+    both running scaled Newton blocks of 8 after the column-wise steps.
     Checks: both true residuals on the host, the duality identity
-    lambda^T b = g^T x, and sampled gradient entries of the CSR values."""
+    lambda^T b = g^T x, the oracle's forward and adjoint solutions (same
+    block sizes, 1e-8 relative), and sampled gradient entries of the CSR
+    values."""
     import torch
     A, b, xs = W.banded_problem(1_000_000, seed=4, band=1000)
     M = csr(A)
     G = lib.Matrix.from_csr(A)
-    opts = dict(s_max=32, restart=128, tol=1e-12, max_restarts=200)
+    opts = dict(s_max=8, restart=128, tol=1e-12, max_restarts=200)
     vals = torch.tensor(A.val, device="cuda", requires_grad=True)
     bt = torch.tensor(b, device="cuda", requires_grad=True)
-    x = lib.sstep_solve(vals, bt, G, **opts)
+    trace = []
+    x = lib.sstep_solve(vals, bt, G, trace=trace, **opts)
     loss = 0.5 * ((x - torch.tensor(xs, device="cuda")) ** 2).sum()
     loss.backward()
     xh = x.detach().cpu().numpy()
@@ -159,6 +200,12 @@ def test_banded_1m_adjoint(lib):
     assert np.linalg.norm(b - M @ xh) <= 1e-12 * np.linalg.norm(b)
     assert np.linalg.norm(g - M.T @ lam) <= 1e-12 * np.linalg.norm(g)
     assert abs(lam @ b - g @ xh) <= 1e-10 * np.linalg.norm(lam) * np.linalg.norm(b)
+    oo = o.Options(**opts)
+    ref_f = o.solve(M, b, opts=oo)
+    ref_a = o.solve(M.T.tocsr(), ref_f.x - xs, opts=oo)
+    for (kind, r), ref, v in zip(trace, (ref_f, ref_a), (xh, lam)):
+        assert list(r.s_hist) == ref.s_hist and max(ref.s_hist) == 8, kind
+        assert np.linalg.norm(v - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
     rng = np.random.default_rng(21)
     ks = rng.choice(A.nnz, 4096, replace=False)
     rows = np.searchsorted(A.row_ptr, ks, side="right") - 1
@@ -191,7 +238,7 @@ def test_aniso4096_fp32_ir_one_outer_step(lib):
     # backward w.r.t. b: the transposed solve with the same options
     bt = torch.tensor(b, device="cuda", requires_grad=True)
     vals = torch.tensor(A.val, device="cuda")
-    xg = lib.sstep_solve(vals, bt, G, **kw)
+    xg = lib.sstep_solve(vals, bt, G, allow_not_converged=True, **kw)
     (0.5 * (xg ** 2).sum()).backward()
     lam = bt.grad.cpu().numpy()
     xgh = xg.detach().cpu().numpy()

@@ -163,6 +163,17 @@ def test_solve_given_shifts_use_the_estimator(lib):
     assert list(gpu.s_hist) == ref.s_hist
 
 
+def aniso2d_kappa(nx, ratio=1e-3, angle_deg=30.0):
+    """2-norm condition number of the 5-point anisotropic operator of
+    workloads.aniso_diffusion_2d on an nx^2 Dirichlet grid, from its
+    closed-form eigenvalues 2 Kxx (1 - cos a) + 2 Kyy (1 - cos b)."""
+    a = np.radians(angle_deg)
+    kxx = np.cos(a) ** 2 + ratio * np.sin(a) ** 2
+    kyy = np.sin(a) ** 2 + ratio * np.cos(a) ** 2
+    c1, cn = np.cos(np.pi / (nx + 1)), np.cos(nx * np.pi / (nx + 1))
+    return (2 * (kxx + kyy) * (1 - cn)) / (2 * (kxx + kyy) * (1 - c1))
+
+
 def test_solve_anisotropic_s200_one_cycle(lib):
     """The 4096^2 workload's shape at 64^2: 200 pre-phase steps, then the
     estimator's step size (200) with partial CholQR truncation, restart 400;
@@ -179,7 +190,7 @@ def test_solve_anisotropic_s200_one_cycle(lib):
     h, hr = np.array(gpu.res_hist), np.array(ref.res_hist)
     assert np.all(np.abs(h - hr) <= 1e-6 * hr + 1e-13)
     x = gpu.x.cpu().numpy()
-    assert np.linalg.norm(x - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
+    assert np.linalg.norm(x - ref.x) <= 1e-8 * np.linalg.norm(ref.x)
 
 
 def test_fp32_ir_anisotropic_s200(lib):
@@ -199,4 +210,9 @@ def test_fp32_ir_anisotropic_s200(lib):
     assert gpu.status == lib.OK and ir.status == "ok"
     assert np.linalg.norm(b - M @ x) <= 1e-10 * np.linalg.norm(b)
     assert abs(gpu.info["outer_iters"] - ir.outer) <= 1
-    assert np.linalg.norm(x - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
+    # both iterates have true residuals <= 1e-10, so each lies within
+    # kappa(A) times its residual of the exact solution (kappa from the
+    # closed-form eigenvalues of the 5-point operator, 1.7e3)
+    true = np.linalg.norm(b - M @ x) / np.linalg.norm(b)
+    bound = aniso2d_kappa(64) * (true + ref.rel_res_true)
+    assert np.linalg.norm(x - ref.x) <= bound * np.linalg.norm(ref.x)

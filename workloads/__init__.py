@@ -300,7 +300,7 @@ CONFIGS = {
     "varcd3d_192": dict(make=lambda: var_conv_diff_3d(192, 3), seed=3,
                         s_max=128, restart=256, tol=1e-10, precond="jacobi"),
     "banded_1m": dict(make=lambda: banded_random(1_000_000, 1000, 26, 4),
-                      seed=4, s_max=32, restart=128, tol=1e-12,
+                      seed=4, s_max=8, restart=128, tol=1e-12,
                       precond="none"),
     "aniso2d_4096": dict(make=lambda: aniso_diffusion_2d(4096), seed=5,
                          s_max=200, restart=400, tol=1e-10, precond="none"),
