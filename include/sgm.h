@@ -18,7 +18,9 @@
  *  - The caller owns every buffer it passes.  The library allocates device
  *    memory only in sgm_matrix_create (the analysed copies of the matrix) and
  *    frees it in sgm_matrix_destroy.  Scratch for a solve is the caller's
- *    workspace, sized by sgm_workspace_size.
+ *    workspace, sized by sgm_workspace_size.  The one exception is
+ *    sgm_block_orth_noalloc, whose scratch is a static device array of the
+ *    library (24 MiB per GPU, for the life of the process).
  *  - Arguments are validated on the host before any HIP call; invalid ones
  *    return SGM_EINVAL and enqueue nothing.  HIP errors return SGM_EHIP.
  *    sgm_last_error() gives a thread-local message for the last failure.
@@ -232,6 +234,24 @@ sgm_status sgm_block_orth(sgm_precision precision, int64_t n_rows, void* Q,
                           sgm_orth orth, void* ws, size_t ws_bytes,
                           void* stream, int32_t* p, double* R_top,
                           double* R_kk);
+
+/* sgm_block_orth without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same block
+ * orthogonalisation, arguments, outputs and errors as sgm_block_orth.  It
+ * calls no hipMalloc/hipFree and takes no workspace: its scratch (partial
+ * sums, the Gram matrices, both partial Cholesky factors and inverses, the
+ * control words) is a device array of 24 MiB inside the library, one copy
+ * per GPU, held until the process ends.  Limits: 1 <= s <= 64 and
+ * i + s <= 256; larger blocks return SGM_EINVAL (use sgm_block_orth).
+ * Every call on one GPU uses that GPU's array, and it keeps the last
+ * call's contents: calls that overlap on one GPU (two host threads, or
+ * two streams whose calls are not ordered) race and give wrong results.
+ * Like sgm_block_orth it synchronises `stream` before returning. */
+sgm_status sgm_block_orth_noalloc(sgm_precision precision, int64_t n_rows,
+                                  void* Q, int64_t ldq, int32_t i, int32_t s,
+                                  double omega, sgm_orth orth, void* stream,
+                                  int32_t* p, double* R_top, double* R_kk);
 
 /* Shifts from a Hessenberg matrix (Sec. 3.4-3.5) computed on the GPU:
  * H (device, leading m0 x m0 block of an upper Hessenberg matrix,

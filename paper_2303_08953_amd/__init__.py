@@ -96,6 +96,10 @@ _SIGS = [
      [C.c_int, C.c_int64, _P, C.c_int64, C.c_int32, C.c_int32, C.c_double,
       C.c_int, _P, C.c_size_t, _P, C.POINTER(C.c_int32),
       C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    ("sgm_block_orth_noalloc", C.c_int,
+     [C.c_int, C.c_int64, _P, C.c_int64, C.c_int32, C.c_int32, C.c_double,
+      C.c_int, _P, C.POINTER(C.c_int32), C.POINTER(C.c_double),
+      C.POINTER(C.c_double)]),
     ("sgm_shifts_ws_size", C.c_size_t, [C.c_int32]),
     ("sgm_shifts", C.c_int,
      [_P, C.c_int32, C.c_int32, C.c_int, C.c_double, C.c_double, _P,
@@ -342,6 +346,22 @@ def block_orth(Q, n_rows, ldq, i, s, omega=0.0, precision="fp64",
                             C.c_size_t(nbytes), _stream(stream), C.byref(p),
                             Rt.ctypes.data_as(C.POINTER(C.c_double)),
                             Rk.ctypes.data_as(C.POINTER(C.c_double))))
+    return p.value, Rt.reshape(s, i).T.copy(), Rk.reshape(s, s).T.copy()
+
+
+def block_orth_noalloc(Q, n_rows, ldq, i, s, omega=0.0, precision="fp64",
+                       stream=None, orth="bcgs2"):
+    """sgm_block_orth_noalloc: block_orth with the library's static device
+    scratch instead of a workspace (no device allocation in the call;
+    s <= 64, i + s <= 256).  Returns (p, R_top (i x s), R_kk (s x s))."""
+    p = C.c_int32()
+    Rt = np.zeros(i * s, dtype=np.float64)
+    Rk = np.zeros(s * s, dtype=np.float64)
+    _check(lib().sgm_block_orth_noalloc(
+        PRECISION[precision], int(n_rows), _ptr(Q), int(ldq), int(i), int(s),
+        float(omega), ORTH[orth], _stream(stream), C.byref(p),
+        Rt.ctypes.data_as(C.POINTER(C.c_double)),
+        Rk.ctypes.data_as(C.POINTER(C.c_double))))
     return p.value, Rt.reshape(s, i).T.copy(), Rk.reshape(s, s).T.copy()
 
 

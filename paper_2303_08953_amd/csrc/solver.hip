@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -824,6 +825,113 @@ void block_layout(Arena& a, Work& w, int i, int s, int64_t n_rows) {
   w.ctrl = a.take<int>(C_NCTRL + 1);
 }
 
+// ------------------------------------------------------- static scratch
+// Device memory of sgm_block_orth_noalloc, for callers that cannot
+// allocate: the small matrices of one block (W, R2, the combined R, the
+// Gram matrices, both partial Cholesky factors and their inverses, the
+// partial Cholesky scratch, the control words) and, in the rest, the
+// partial sums of the grid reductions.  One copy per GPU, held until the
+// process ends; every call on a GPU shares it, so overlapping calls on one
+// GPU race.  Nothing in it needs to start at zero: every kernel writes the
+// words it later reads in the same call.
+constexpr size_t kStaticScratchDoubles = (size_t)3 << 20;  // 24 MiB
+constexpr int kNoAllocMaxS = 64;       // block columns
+constexpr int kNoAllocMaxCols = 256;   // prior + block columns (i + s)
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device
+// with that device current (the array's name is only a host-side stand-in
+// in host code).
+double* static_scratch() {
+  int dev = -1;
+  SGM_HIP(hipGetDevice(&dev));
+  SGM_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_dev[dev] == nullptr) {
+    void* ptr = nullptr;
+    SGM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    SGM_REQUIRE(ptr != nullptr, "static scratch has no device address");
+    g_scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_dev[dev];
+}
+
+// block_layout in the static array: the small matrices first, then the
+// partial sums in everything that is left (the reductions pick their row
+// chunk counts to fit it).
+void block_layout_static(Arena& a, Work& w, int i, int s) {
+  w.ldw = std::max(i, 1) + s;
+  w.lds = s;
+  const int64_t ws = (int64_t)w.ldw * s, ss = (int64_t)s * s;
+  w.W = a.take<double>(ws);
+  w.R2 = a.take<double>(ws);
+  w.Rtop = a.take<double>(ws);
+  w.G = a.take<double>(ss);
+  w.G2 = a.take<double>(ss);
+  w.Z = a.take<double>(ss);
+  w.Zinv = a.take<double>(ss);
+  w.Zt = a.take<double>(ss);
+  w.Ztinv = a.take<double>(ss);
+  w.Rkk = a.take<double>(ss);
+  w.pchol_scr = a.take<double>(2 * ss + 2 * s);
+  w.ctrl = a.take<int>(C_NCTRL + 1);
+  a.off = (size_t)round_up((int64_t)a.off, 256);
+  const int64_t left =
+      ((int64_t)(kStaticScratchDoubles * sizeof(double)) - (int64_t)a.off) /
+      (int64_t)sizeof(double);
+  if (left < 8 * (int64_t)w.ldw * s)
+    throw Error{SGM_EINVAL, "static scratch too small for this block"};
+  w.P.cap = left;
+  w.P.buf = a.take<double>(left);
+}
+
+// The block orthogonalisation and the read-back shared by sgm_block_orth
+// and sgm_block_orth_noalloc (w laid out by the caller).
+void run_block_orth(sgm_precision precision, void* Q, int64_t ldq, int32_t i,
+                    int32_t s, double omega, sgm_orth orth, Work& w,
+                    hipStream_t st, int32_t* p, double* R_top, double* R_kk) {
+  const bool f32 = precision == SGM_FP32_IR;
+  const double om = omega > 0 ? omega : default_omega(f32);
+  const bool pyth = orth == SGM_ORTH_BCGS2_PYTH;
+  if (f32)
+    orth_block<float>(colmajor_view<float>(static_cast<float*>(Q), ldq), ldq,
+                      i, s, om, w, st, true, pyth);
+  else
+    orth_block<double>(colmajor_view<double>(static_cast<double*>(Q), ldq),
+                       ldq, i, s, om, w, st, true, pyth);
+  int ctrl[C_NCTRL];
+  SGM_HIP(hipMemcpyAsync(ctrl, w.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost,
+                         st));
+  if (R_top)
+    SGM_HIP(hipMemcpy2DAsync(R_top, sizeof(double) * (size_t)i, w.Rtop,
+                             sizeof(double) * (size_t)w.ldw,
+                             sizeof(double) * (size_t)i, (size_t)s,
+                             hipMemcpyDeviceToHost, st));
+  if (R_kk)
+    SGM_HIP(hipMemcpyAsync(R_kk, w.Rkk, sizeof(double) * (size_t)s * s,
+                           hipMemcpyDeviceToHost, st));
+  SGM_HIP(hipStreamSynchronize(st));
+  *p = ctrl[C_P2];
+}
+
+void check_block_args(sgm_precision precision, int64_t n_rows, void* Q,
+                      int64_t ldq, int32_t i, int32_t s, double omega,
+                      sgm_orth orth, int32_t* p) {
+  SGM_REQUIRE(Q != nullptr && p != nullptr, "NULL argument");
+  SGM_REQUIRE(n_rows >= 1 && ldq >= n_rows && ldq % kLdAlign == 0,
+              "ldq must be >= n_rows and a multiple of 64");
+  SGM_REQUIRE(i >= 1 && s >= 1 && s <= 256, "need i >= 1 and 1 <= s <= 256");
+  SGM_REQUIRE(precision == SGM_FP64 || precision == SGM_FP32_IR,
+              "unknown precision");
+  SGM_REQUIRE(omega >= 0.0, "omega must be >= 0");
+  SGM_REQUIRE(orth == SGM_ORTH_BCGS2 || orth == SGM_ORTH_BCGS2_PYTH,
+              "unknown orth");
+}
+
 void shifts_layout(Arena& a, Work& w, int m0) {
   w.wr = a.take<double>(m0);
   w.wi = a.take<double>(m0);
@@ -1073,15 +1181,7 @@ sgm_status sgm_block_orth(sgm_precision precision, int64_t n_rows, void* Q,
                           void* stream, int32_t* p, double* R_top,
                           double* R_kk) {
   SGM_API_BEGIN
-  SGM_REQUIRE(Q != nullptr && p != nullptr, "NULL argument");
-  SGM_REQUIRE(n_rows >= 1 && ldq >= n_rows && ldq % kLdAlign == 0,
-              "ldq must be >= n_rows and a multiple of 64");
-  SGM_REQUIRE(i >= 1 && s >= 1 && s <= 256, "need i >= 1 and 1 <= s <= 256");
-  SGM_REQUIRE(precision == SGM_FP64 || precision == SGM_FP32_IR,
-              "unknown precision");
-  SGM_REQUIRE(omega >= 0.0, "omega must be >= 0");
-  SGM_REQUIRE(orth == SGM_ORTH_BCGS2 || orth == SGM_ORTH_BCGS2_PYTH,
-              "unknown orth");
+  check_block_args(precision, n_rows, Q, ldq, i, s, omega, orth, p);
   const size_t need = sgm_block_ws_size(n_rows, i, s);
   SGM_REQUIRE(ws != nullptr && ws_bytes >= need, "workspace too small");
   Arena a;
@@ -1089,29 +1189,28 @@ sgm_status sgm_block_orth(sgm_precision precision, int64_t n_rows, void* Q,
       round_up(reinterpret_cast<int64_t>(ws), 256));
   Work w;
   block_layout(a, w, i, s, n_rows);
-  hipStream_t st = as_stream(stream);
-  const bool f32 = precision == SGM_FP32_IR;
-  const double om = omega > 0 ? omega : default_omega(f32);
-  const bool pyth = orth == SGM_ORTH_BCGS2_PYTH;
-  if (f32)
-    orth_block<float>(colmajor_view<float>(static_cast<float*>(Q), ldq), ldq,
-                      i, s, om, w, st, true, pyth);
-  else
-    orth_block<double>(colmajor_view<double>(static_cast<double*>(Q), ldq),
-                       ldq, i, s, om, w, st, true, pyth);
-  int ctrl[C_NCTRL];
-  SGM_HIP(hipMemcpyAsync(ctrl, w.ctrl, sizeof(ctrl), hipMemcpyDeviceToHost,
-                         st));
-  if (R_top)
-    SGM_HIP(hipMemcpy2DAsync(R_top, sizeof(double) * (size_t)i, w.Rtop,
-                             sizeof(double) * (size_t)w.ldw,
-                             sizeof(double) * (size_t)i, (size_t)s,
-                             hipMemcpyDeviceToHost, st));
-  if (R_kk)
-    SGM_HIP(hipMemcpyAsync(R_kk, w.Rkk, sizeof(double) * (size_t)s * s,
-                           hipMemcpyDeviceToHost, st));
-  SGM_HIP(hipStreamSynchronize(st));
-  *p = ctrl[C_P2];
+  run_block_orth(precision, Q, ldq, i, s, omega, orth, w, as_stream(stream),
+                 p, R_top, R_kk);
+  return SGM_OK;
+  SGM_API_END
+}
+
+sgm_status sgm_block_orth_noalloc(sgm_precision precision, int64_t n_rows,
+                                  void* Q, int64_t ldq, int32_t i, int32_t s,
+                                  double omega, sgm_orth orth, void* stream,
+                                  int32_t* p, double* R_top, double* R_kk) {
+  SGM_API_BEGIN
+  check_block_args(precision, n_rows, Q, ldq, i, s, omega, orth, p);
+  SGM_REQUIRE(s <= kNoAllocMaxS && i + s <= kNoAllocMaxCols,
+              "sgm_block_orth_noalloc: needs s <= 64 and i + s <= 256 (its "
+              "static scratch holds 24 MiB); use sgm_block_orth for larger "
+              "blocks");
+  Arena a;
+  a.base = reinterpret_cast<char*>(static_scratch());
+  Work w;
+  block_layout_static(a, w, i, s);
+  run_block_orth(precision, Q, ldq, i, s, omega, orth, w, as_stream(stream),
+                 p, R_top, R_kk);
   return SGM_OK;
   SGM_API_END
 }
