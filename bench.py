@@ -108,6 +108,41 @@ def measure_triad(torch, nbytes=1 << 30, reps=10):
     return 3 * n * 8 / (ms * 1e-3) / 1e9
 
 
+def stream_probe(torch, nbytes=1 << 30, reps=10):
+    """Achievable HBM rates of plain streams with the read/write mixes of
+    the solver's kernels, from PyTorch's own elementwise and reduction
+    kernels on float64 vectors of nbytes each (cold in the 256 MB Infinity
+    Cache): read-only (sum), 1 read : 1 write (copy), 2 : 1 (add), 3 : 1
+    (addcmul).  GB/s counting every vector read and written once."""
+    n = nbytes // 8
+    vs = [torch.rand(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    a, b, c, d = vs
+    red = torch.empty((), dtype=torch.float64, device="cuda")
+    cases = {
+        "read_only": (lambda: torch.sum(a, 0, out=red), 1),
+        "read1_write1": (lambda: d.copy_(a), 2),
+        "read2_write1": (lambda: torch.add(a, b, alpha=0.5, out=d), 3),
+        "read3_write1": (lambda: torch.addcmul(a, b, c, value=0.5, out=d), 4),
+    }
+    out = {}
+    for name, (f, nvec) in cases.items():
+        for _ in range(2):
+            f()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = round(nvec * n * 8 / (ms * 1e-3) / 1e9, 1)
+    del vs, a, b, c, d
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(A, b, gpu_iters, restart, s_max):
     """The oracle, as it stands, on one restart cycle of the same solve.
 
@@ -266,7 +301,7 @@ def study(args, np, torch, sgm, W):
     for mname, o in modes:
         cap = dict(o, max_restarts=0, max_outer=1)
         t0 = time.perf_counter()
-        sgm.solve(G, b, out=x, workspace=ws, **cap)
+        sgm.solve(G, b, out=x, workspace=ws, mpk_depth=args.mpk_depth, **cap)
         torch.cuda.synchronize()
         log(f"[bench] warmup {mname}: {(time.perf_counter() - t0) * 1e3:.0f}"
             " ms")
@@ -275,7 +310,8 @@ def study(args, np, torch, sgm, W):
     for k in range(args.steps):
         for mname, o in modes:
             t0 = time.perf_counter()
-            r = sgm.solve(G, b, out=x, workspace=ws, **o)
+            r = sgm.solve(G, b, out=x, workspace=ws,
+                          mpk_depth=args.mpk_depth, **o)
             torch.cuda.synchronize()
             ms = (time.perf_counter() - t0) * 1e3
             per.setdefault(mname, []).append(ms)
@@ -410,6 +446,12 @@ def main():
                     help="aniso2d_4096 only: restart cycles (float64) and "
                          "outer steps (float32-IR), default 5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mpk-depth", type=int, default=1,
+                    help="matrix powers steps per pass over the matrix "
+                         "(temporal blocking, 1-4) for every mode")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only measure plain HBM stream rates (read-only, "
+                         "1:1, 2:1 and 3:1 read/write) and print them")
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="run one plain device copy of this size (for the "
                          "rocprof counter calibration)")
@@ -435,6 +477,11 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
         log(f"[bench] calibration copy of {args.calibrate_copy_mb} MiB done")
+    if args.stream_probe:
+        print(json.dumps({"stream_probe_gbs": stream_probe(torch),
+                          "vector_bytes": 1 << 30, "dtype": "f64"}),
+              flush=True)
+        return
     if args.workload != "poisson3d_128":
         print(json.dumps(study(args, np, torch, sgm, W)), flush=True)
         return
@@ -466,7 +513,8 @@ def main():
 
     def run(opts):
         t0 = time.perf_counter()
-        r = sgm.solve(G, b, out=x, workspace=ws, **opts)
+        r = sgm.solve(G, b, out=x, workspace=ws,
+                      **dict(dict(mpk_depth=args.mpk_depth), **opts))
         torch.cuda.synchronize()
         return r, (time.perf_counter() - t0) * 1e3
 

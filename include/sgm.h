@@ -147,6 +147,11 @@ typedef struct {
   sgm_orth orth;          /* second BCGS pass of blocks with s >= 2 (the
                              column-wise s = 1 steps always use Alg. 4's);
                              default SGM_ORTH_BCGS2                          */
+  int32_t mpk_depth;      /* matrix powers steps per pass over the matrix
+                             (temporal blocking, 1..4; default 1 = one SpMV
+                             launch per step).  Results are bitwise those
+                             of depth 1; matrices with fewer than three row
+                             slabs of at least their bandwidth run depth 1 */
 } sgm_opts;
 
 /* Fills *o (host) with the defaults: s_max 8, restart 64, max_restarts 100,
@@ -177,6 +182,8 @@ typedef struct {
   int64_t n_spmv;         /* SpMV launches of the matrix powers kernel       */
   double t_spmv_ms;       /* their GPU time: one HIP event pair around the
                              back-to-back launches of each block's MPK       */
+  int32_t mpk_depth;      /* depth the matrix powers kernel ran at           */
+  int64_t mpk_slab_rows;  /* rows per slab of the fused kernel (0: depth 1) */
 } sgm_info;
 
 /* Bytes of device workspace sgm_solve needs for this matrix and options. */
@@ -217,6 +224,22 @@ sgm_status sgm_grad_vals(sgm_matrix A, const double* lambda, const double* x,
 sgm_status sgm_mpk(sgm_matrix A, int transpose, sgm_precision precision,
                    void* Q, int64_t ldq, int32_t c, int32_t s,
                    const double* records, int32_t n_rec, void* stream);
+
+/* The matrix powers kernel of sgm_mpk with temporal blocking (the
+ * communication-avoiding matrix powers idea of Sec. 2, applied to the
+ * cache hierarchy): `depth` (1..4) consecutive steps per pass over the
+ * matrix.  The rows are cut into slabs of at least the matrix bandwidth
+ * max |column - row|; launch L computes step j on slab L - 2 j, so every
+ * slab's matrix rows serve its `depth` steps within a few launches, while
+ * they are still cached.  Q, ldq, c, s, records, n_rec, transpose and
+ * precision as in sgm_mpk; the results are bitwise those of sgm_mpk
+ * (every row is computed by the same arithmetic).  *slab_rows (host, may
+ * be NULL) receives the slab height, or 0 when the matrix has fewer than
+ * three such slabs and the call ran one step per launch. */
+sgm_status sgm_mpk_fused(sgm_matrix A, int transpose, sgm_precision precision,
+                         void* Q, int64_t ldq, int32_t c, int32_t s,
+                         const double* records, int32_t n_rec, int32_t depth,
+                         void* stream, int64_t* slab_rows);
 
 /* Block orthogonalisation of the s columns Q[:, i .. i+s-1] against the
  * orthonormal Q[:, 0 .. i-1]: BCGS2 with two partial CholQR passes

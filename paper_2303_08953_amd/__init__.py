@@ -46,7 +46,7 @@ class Opts(C.Structure):
         ("ritz_reuse", C.c_int32),
         ("shifts_host", C.POINTER(C.c_double)), ("n_shifts", C.c_int32),
         ("prephase", C.c_int), ("prephase_s", C.c_int32),
-        ("orth", C.c_int),
+        ("orth", C.c_int), ("mpk_depth", C.c_int32),
     ]
 
 
@@ -60,6 +60,7 @@ class Info(C.Structure):
         ("rel_res_true", C.c_double), ("rel_res_est", C.c_double),
         ("t_phase_ms", C.c_double * 8),
         ("n_spmv", C.c_int64), ("t_spmv_ms", C.c_double),
+        ("mpk_depth", C.c_int32), ("mpk_slab_rows", C.c_int64),
     ]
 
     def as_dict(self):
@@ -91,6 +92,9 @@ _SIGS = [
     ("sgm_mpk", C.c_int,
      [_P, C.c_int, C.c_int, _P, C.c_int64, C.c_int32, C.c_int32, _P,
       C.c_int32, _P]),
+    ("sgm_mpk_fused", C.c_int,
+     [_P, C.c_int, C.c_int, _P, C.c_int64, C.c_int32, C.c_int32, _P,
+      C.c_int32, C.c_int32, _P, C.POINTER(C.c_int64)]),
     ("sgm_block_ws_size", C.c_size_t, [C.c_int64, C.c_int32, C.c_int32]),
     ("sgm_block_orth", C.c_int,
      [C.c_int, C.c_int64, _P, C.c_int64, C.c_int32, C.c_int32, C.c_double,
@@ -229,7 +233,7 @@ def make_opts(s_max=8, restart=64, max_restarts=100, tol=1e-10,
               precond="none", basis="scaled_newton", precision="fp64",
               omega=0.0, omega_est=0.0, use_estimator=True, transpose=False,
               inner_tol=1e-6, max_outer=200, ritz_reuse=True, shifts=None,
-              prephase="cgs2", prephase_s=8, orth="bcgs2"):
+              prephase="cgs2", prephase_s=8, orth="bcgs2", mpk_depth=1):
     o = Opts()
     lib().sgm_opts_default(C.byref(o))
     o.s_max, o.restart, o.max_restarts, o.tol = s_max, restart, max_restarts, tol
@@ -244,6 +248,7 @@ def make_opts(s_max=8, restart=64, max_restarts=100, tol=1e-10,
     o.prephase = PREPHASE[prephase]
     o.prephase_s = int(prephase_s)
     o.orth = ORTH[orth]
+    o.mpk_depth = int(mpk_depth)
     keep = None
     if shifts is not None:
         z = np.asarray(shifts, dtype=np.complex128).ravel()
@@ -327,6 +332,22 @@ def mpk(A: Matrix, Q, ldq, c, s, records, transpose=False, precision="fp64",
                          _ptr(Q), int(ldq), int(c), int(s), _ptr(rec),
                          rec.numel() // 3, _stream(stream)))
     torch.cuda.current_stream().synchronize()
+
+
+def mpk_fused(A: Matrix, Q, ldq, c, s, records, depth, transpose=False,
+              precision="fp64", stream=None):
+    """sgm_mpk_fused (temporal blocking, `depth` steps per pass) on a
+    column-major Q given as a flat device tensor.  Returns the slab height
+    in rows (0 when it ran one step per launch)."""
+    torch = _torch()
+    rec = _dev(np.asarray(records, dtype=np.float64).ravel(), torch.float64)
+    slab = C.c_int64()
+    _check(lib().sgm_mpk_fused(A.handle, int(transpose), PRECISION[precision],
+                               _ptr(Q), int(ldq), int(c), int(s), _ptr(rec),
+                               rec.numel() // 3, int(depth), _stream(stream),
+                               C.byref(slab)))
+    torch.cuda.current_stream().synchronize()
+    return slab.value
 
 
 def block_orth(Q, n_rows, ldq, i, s, omega=0.0, precision="fp64",

@@ -133,6 +133,7 @@ struct Matrix {
   int32_t* row_of = nullptr;   // row index of every nonzero
   double* val = nullptr;       // current values, CSR order
   double* diag = nullptr;      // [n]
+  int64_t bandwidth = 0;       // max |column - row| over the nonzeros
   Sell fwd;                    // A
   Sell trn;                    // A^T
   // Jacobi-scaled value copies (A D^{-1}), built on demand inside a solve's
@@ -164,6 +165,34 @@ void spmv_plain(const Sell& S, const T* val, const T* x, T* y,
 template <typename T>
 void spmv_mpk(const Sell& S, const T* val, QView<T> Q, int jx, int jprev,
               int jy, const double* rec, int j, hipStream_t st);
+// Depth-k matrix powers kernel (temporal blocking over row slabs): the
+// steps j of one block, each y = column ycol from x = column xcol (and the
+// previous vector, column pcol, when pcol >= 0) with records rec[3 j..].
+struct MpkStep {
+  int xcol, pcol, ycol, j;
+};
+constexpr int kMaxMpkTasks = 4;  // deepest fusion (steps per pass)
+struct MpkTask {
+  int64_t s0, ns;  // slices [s0, s0 + ns)
+  int xcol, pcol, ycol, j;
+};
+struct MpkTasks {
+  MpkTask t[kMaxMpkTasks];
+  int wg[kMaxMpkTasks + 1];  // first workgroup of each piece (multiples of 8)
+  int count;
+};
+struct MpkPlan {
+  int depth = 1;             // steps per pass over the matrix (1 = unfused)
+  int64_t slab_slices = 0;   // slices per row slab
+  int64_t nslabs = 0;
+};
+// The slab plan for a depth (falls back to depth 1 when the matrix has
+// fewer than three slabs of at least its bandwidth).
+MpkPlan mpk_plan(const Sell& S, int64_t bandwidth, int depth, int vbytes);
+template <typename T>
+void spmv_mpk_steps(const Sell& S, const T* val, QView<T> Q,
+                    const MpkStep* steps, int nsteps, const double* rec,
+                    const MpkPlan& plan, hipStream_t st);
 // r = b - A x (float64) and per-block partial sums of r^2 into part[];
 // returns the number of partials written.
 int64_t spmv_resid(const Sell& S, const double* val, const double* x,

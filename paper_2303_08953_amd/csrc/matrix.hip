@@ -270,6 +270,19 @@ void matrix_extract_diag(Matrix& M, hipStream_t st) {
   SGM_CHECK_LAUNCH();
 }
 
+// max |column - row| over the nonzeros (integer maximum: deterministic)
+__global__ void k_bandwidth(const int32_t* row_of, const int32_t* col,
+                            int64_t nnz, int* out) {
+  int m = 0;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int d = col[k] - row_of[k];
+    m = max(m, d < 0 ? -d : d);
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+  if (threadIdx.x % kWave == 0) atomicMax(out, m);
+}
+
 Matrix* matrix_create(int64_t n, int64_t nnz, const int32_t* rp,
                       const int32_t* col, const double* val, hipStream_t st) {
   Matrix* M = new Matrix();
@@ -312,6 +325,18 @@ Matrix* matrix_create(int64_t n, int64_t nnz, const int32_t* rp,
     hipLaunchKernelGGL(k_row_of, dim3(grid1(n)), dim3(256), 0, st,
                        M->row_ptr, n, M->row_of);
     SGM_CHECK_LAUNCH();
+    SGM_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+    if (nnz > 0) {
+      const int64_t gb = grid1(nnz) < 4096 ? grid1(nnz) : 4096;
+      hipLaunchKernelGGL(k_bandwidth, dim3((unsigned)gb), dim3(256), 0, st,
+                         M->row_of, M->col, nnz, bad);
+      SGM_CHECK_LAUNCH();
+    }
+    int hbw = 0;
+    SGM_HIP(hipMemcpyAsync(&hbw, bad, sizeof(int), hipMemcpyDeviceToHost,
+                           st));
+    SGM_HIP(hipStreamSynchronize(st));
+    M->bandwidth = hbw;
     matrix_extract_diag(*M, st);
     // forward SELL
     sell_build(M->fwd, n, M->row_ptr, M->col, nullptr, st);

@@ -292,6 +292,8 @@ struct Result {
   int s0 = 0, s_init = 0, n_rec = 0, hits = 0;
   int64_t n_spmv = 0;
   double t_spmv = 0.0;
+  int mpk_depth = 1;
+  int64_t mpk_slab_rows = 0;
 };
 
 template <typename T>
@@ -311,6 +313,8 @@ struct Engine {
   Shifts sh;
   Result& res;
   hipEvent_t ev[4];
+  MpkPlan mplan;
+  std::vector<MpkStep> msteps;
 
   Engine(const Matrix& A_, const Sell& S_, const T* v, const double* v64,
          Work& w_, HostMirror hm_, hipStream_t st_, const sgm_opts& o_,
@@ -321,6 +325,9 @@ struct Engine {
     omega = o.omega > 0 ? o.omega : default_omega(f32);
     eps = unit_roundoff(f32);
     for (auto& e : ev) SGM_HIP(hipEventCreate(&e));
+    mplan = mpk_plan(S, A.bandwidth, o.mpk_depth, (int)sizeof(T));
+    res.mpk_depth = mplan.depth;
+    res.mpk_slab_rows = mplan.depth > 1 ? mplan.slab_slices * kSlice : 0;
   }
   ~Engine() {
     for (auto& e : ev) (void)hipEventDestroy(e);
@@ -407,12 +414,14 @@ struct Engine {
     const double* rec = mono ? w.mono : w.rec;
     const int nrec = mono ? 1 : sh.n_rec;
     SGM_HIP(hipEventRecord(ev[0], st));
+    msteps.resize(s_eff);
     for (int j = 0; j < s_eff; ++j) {
       const int q = j % nrec;
       const double delta = mono ? 0.0 : sh.rec[3 * q + 2];
       const int jprev = (j >= 1 && delta != 0.0) ? nb - 2 + j : -1;
-      spmv_mpk<T>(S, vals, Q(), nb - 1 + j, jprev, nb + j, rec, q, st);
+      msteps[j] = MpkStep{nb - 1 + j, jprev, nb + j, q};
     }
+    spmv_mpk_steps<T>(S, vals, Q(), msteps.data(), s_eff, rec, mplan, st);
     SGM_HIP(hipEventRecord(ev[1], st));
     orth_block<T>(Q(), ld, nb, s_eff, omega, w, st, false,
                   o.orth == SGM_ORTH_BCGS2_PYTH);
@@ -786,6 +795,8 @@ void validate_opts(const sgm_opts* o) {
   SGM_REQUIRE(o->prephase_s >= 1, "prephase_s must be >= 1");
   SGM_REQUIRE(o->orth == SGM_ORTH_BCGS2 || o->orth == SGM_ORTH_BCGS2_PYTH,
               "unknown orth");
+  SGM_REQUIRE(o->mpk_depth >= 1 && o->mpk_depth <= kMaxMpkTasks,
+              "mpk_depth must be in [1, 4]");
 }
 
 int nshift_max(const sgm_opts& o) {
@@ -1051,6 +1062,7 @@ void sgm_opts_default(sgm_opts* o) {
   o->prephase = SGM_PREPHASE_CGS2;
   o->prephase_s = 8;
   o->orth = SGM_ORTH_BCGS2;
+  o->mpk_depth = 1;
 }
 
 sgm_status sgm_workspace_size(sgm_matrix A, const sgm_opts* o,
@@ -1120,6 +1132,8 @@ sgm_status sgm_solve(sgm_matrix A, const double* b, const double* x0,
     for (int i = 0; i < 8; ++i) info->t_phase_ms[i] = R.t[i];
     info->n_spmv = R.n_spmv;
     info->t_spmv_ms = R.t_spmv;
+    info->mpk_depth = R.mpk_depth;
+    info->mpk_slab_rows = R.mpk_slab_rows;
   }
   if (st < 0) set_error(err);
   return st;
@@ -1163,6 +1177,40 @@ sgm_status sgm_mpk(sgm_matrix A, int transpose, sgm_precision precision,
                       colmajor_view<float>(static_cast<float*>(Q), ldq),
                       c + j, jprev, c + j + 1, records, q, st);
   }
+  return SGM_OK;
+  SGM_API_END
+}
+
+sgm_status sgm_mpk_fused(sgm_matrix A, int transpose, sgm_precision precision,
+                         void* Q, int64_t ldq, int32_t c, int32_t s,
+                         const double* records, int32_t n_rec, int32_t depth,
+                         void* stream, int64_t* slab_rows) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(A != nullptr && Q != nullptr && records != nullptr,
+              "NULL argument");
+  const Matrix& M = *handle(A)->M;
+  SGM_REQUIRE(ldq >= M.n && ldq % kLdAlign == 0,
+              "ldq must be >= n and a multiple of 64");
+  SGM_REQUIRE(c >= 0 && s >= 0 && n_rec >= 1, "bad c/s/n_rec");
+  SGM_REQUIRE(depth >= 1 && depth <= kMaxMpkTasks, "depth must be in [1, 4]");
+  SGM_REQUIRE(precision == SGM_FP64 || precision == SGM_FP32_IR,
+              "unknown precision");
+  const Sell& S = transpose ? M.trn : M.fwd;
+  hipStream_t st = as_stream(stream);
+  std::vector<MpkStep> steps(s > 0 ? s : 1);
+  for (int j = 0; j < s; ++j)
+    steps[j] = MpkStep{c + j, j >= 1 ? c + j - 1 : -1, c + j + 1, j % n_rec};
+  const bool f32 = precision == SGM_FP32_IR;
+  const MpkPlan plan = mpk_plan(S, M.bandwidth, depth, f32 ? 4 : 8);
+  if (slab_rows) *slab_rows = plan.depth > 1 ? plan.slab_slices * kSlice : 0;
+  if (f32)
+    spmv_mpk_steps<float>(S, S.val32,
+                          colmajor_view<float>(static_cast<float*>(Q), ldq),
+                          steps.data(), s, records, plan, st);
+  else
+    spmv_mpk_steps<double>(S, S.val64,
+                           colmajor_view<double>(static_cast<double*>(Q), ldq),
+                           steps.data(), s, records, plan, st);
   return SGM_OK;
   SGM_API_END
 }

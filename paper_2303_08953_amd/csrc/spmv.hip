@@ -10,38 +10,18 @@ namespace {
 constexpr int kSpmvBlock = 256;                    // 4 wavefronts
 constexpr int kSlicesPerBlock = kSpmvBlock / kWave;
 
-// x, xprev and y are columns of a block of vectors with layout XV (row r of
-// a column at column base + XV.row_off(r)); the plain and residual
-// epilogues use contiguous vectors (column-major view).
+// Row r = 64 s + lane of A times x on SELL-C-64 slice s (0 for s past the
+// last slice): the matrix part of every SpMV kernel below, so the fused
+// matrix powers kernel computes bitwise the rows of the one-step kernel.
 // IDX is int32_t (absolute columns) or int16_t (16-bit relative columns:
-// group base kbase[ptr[s] / 64 + w] + lane + offset).
-template <typename T, int EPI, typename IDX>
-__global__ __launch_bounds__(kSpmvBlock) void k_spmv(
+// group base kbase[ptr[s] / 64 + w] + lane + offset).  x is read at
+// XV.row_off(column).
+template <typename T, typename IDX>
+__device__ __forceinline__ T sell_row_dot(
     const int64_t* __restrict__ ptr, const int32_t* __restrict__ width,
     const IDX* __restrict__ col, const int32_t* __restrict__ kbase,
     const T* __restrict__ val, QView<T> XV, const T* __restrict__ x,
-    const T* __restrict__ xprev, T* __restrict__ y,
-    const double* __restrict__ b, double* __restrict__ part, int64_t n,
-    int64_t nslices, const double* __restrict__ rec, int j) {
-  // slice index is wavefront-uniform: its metadata comes in scalar loads
-  const int64_t s = (int64_t)blockIdx.x * kSlicesPerBlock +
-                    __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-  const int lane = threadIdx.x % kWave;
-  const int64_t r = s * kSlice + lane;
-  // the epilogue's own operands are loaded first, so their latency
-  // overlaps the matrix stream instead of following it
-  T xo = 0, xp = 0;
-  int64_t ro = 0;
-  double bb = 0.0;
-  if constexpr (EPI == EPI_MPK) {
-    if (r < n) {
-      ro = XV.row_off(r);
-      xo = x[ro];
-      if (xprev != nullptr) xp = xprev[ro];
-    }
-  } else if constexpr (EPI == EPI_RESID) {
-    if (r < n) bb = b[r];
-  }
+    int64_t nslices, int64_t s, int lane) {
   T sum = 0;
   if (s < nslices) {
     const int64_t p0 = ptr[s];
@@ -73,16 +53,59 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
         if (k + q < w) sum += v[q] * xv[q];
     }
   }
+  return sum;
+}
+
+// The matrix powers recurrence of Eq. (newtonrecurrence) on row r:
+// y = (sum - theta xo - delta xp) / gamma with (theta, gamma, delta) =
+// rec[3 j .. 3 j + 2]; the delta term only when the previous vector is
+// given.
+template <typename T>
+__device__ __forceinline__ T mpk_row(T sum, T xo, T xp, bool has_prev,
+                                     const double* __restrict__ rec, int j) {
+  const T theta = (T)rec[3 * j], gamma = (T)rec[3 * j + 1],
+          delta = (T)rec[3 * j + 2];
+  T v = sum - theta * xo;
+  if (has_prev) v = v - delta * xp;
+  return v / gamma;
+}
+
+// x, xprev and y are columns of a block of vectors with layout XV (row r of
+// a column at column base + XV.row_off(r)); the plain and residual
+// epilogues use contiguous vectors (column-major view).
+template <typename T, int EPI, typename IDX>
+__global__ __launch_bounds__(kSpmvBlock) void k_spmv(
+    const int64_t* __restrict__ ptr, const int32_t* __restrict__ width,
+    const IDX* __restrict__ col, const int32_t* __restrict__ kbase,
+    const T* __restrict__ val, QView<T> XV, const T* __restrict__ x,
+    const T* __restrict__ xprev, T* __restrict__ y,
+    const double* __restrict__ b, double* __restrict__ part, int64_t n,
+    int64_t nslices, const double* __restrict__ rec, int j) {
+  // slice index is wavefront-uniform: its metadata comes in scalar loads
+  const int64_t s = (int64_t)blockIdx.x * kSlicesPerBlock +
+                    __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int64_t r = s * kSlice + lane;
+  // the epilogue's own operands are loaded first, so their latency
+  // overlaps the matrix stream instead of following it
+  T xo = 0, xp = 0;
+  int64_t ro = 0;
+  double bb = 0.0;
+  if constexpr (EPI == EPI_MPK) {
+    if (r < n) {
+      ro = XV.row_off(r);
+      xo = x[ro];
+      if (xprev != nullptr) xp = xprev[ro];
+    }
+  } else if constexpr (EPI == EPI_RESID) {
+    if (r < n) bb = b[r];
+  }
+  const T sum = sell_row_dot<T, IDX>(ptr, width, col, kbase, val, XV, x,
+                                     nslices, s, lane);
   if constexpr (EPI == EPI_PLAIN) {
     if (r < n) y[r] = sum;
   } else if constexpr (EPI == EPI_MPK) {
-    if (r < n) {
-      const T theta = (T)rec[3 * j], gamma = (T)rec[3 * j + 1],
-              delta = (T)rec[3 * j + 2];
-      T v = sum - theta * xo;
-      if (xprev != nullptr) v = v - delta * xp;
-      y[ro] = v / gamma;
-    }
+    if (r < n) y[ro] = mpk_row<T>(sum, xo, xp, xprev != nullptr, rec, j);
   } else {  // EPI_RESID (float64): r = b - A x, partial sums of r^2
     double rr = 0.0;
     if (r < n) {
@@ -100,6 +123,55 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
       part[blockIdx.x] = t;
     }
   }
+}
+
+// One launch of the depth-k matrix powers kernel: up to kMaxMpkTasks
+// (step, row slab) pieces, each the recurrence of one step on the slices
+// [s0, s0 + ns) of one slab.  Piece t owns workgroups [wg[t], wg[t + 1]);
+// every wg[t] is a multiple of 8, so a slab's slices fall on the same XCD
+// (workgroup id mod 8) in every launch that touches the slab.
+template <typename T, typename IDX>
+__global__ __launch_bounds__(kSpmvBlock) void k_mpk_tasks(
+    const int64_t* __restrict__ ptr, const int32_t* __restrict__ width,
+    const IDX* __restrict__ col, const int32_t* __restrict__ kbase,
+    const T* __restrict__ val, QView<T> XV, int64_t n, int64_t nslices,
+    const double* __restrict__ rec, MpkTasks tasks) {
+  const int bid = (int)blockIdx.x;
+  // the piece's fields, selected with constant indices (a run-time index
+  // into the argument struct would copy it to scratch memory)
+  int64_t s0 = tasks.t[0].s0, ns = tasks.t[0].ns;
+  int wg0 = tasks.wg[0], xcol = tasks.t[0].xcol, pcol = tasks.t[0].pcol,
+      ycol = tasks.t[0].ycol, jrec = tasks.t[0].j;
+#pragma unroll
+  for (int u = 1; u < kMaxMpkTasks; ++u)
+    if (u < tasks.count && bid >= tasks.wg[u]) {
+      s0 = tasks.t[u].s0;
+      ns = tasks.t[u].ns;
+      wg0 = tasks.wg[u];
+      xcol = tasks.t[u].xcol;
+      pcol = tasks.t[u].pcol;
+      ycol = tasks.t[u].ycol;
+      jrec = tasks.t[u].j;
+    }
+  const int64_t local = (int64_t)(bid - wg0) * kSlicesPerBlock +
+                        __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (local >= ns) return;
+  const int64_t s = s0 + local;
+  const int lane = threadIdx.x % kWave;
+  const int64_t r = s * kSlice + lane;
+  const T* x = XV.col(xcol);
+  const T* xprev = pcol >= 0 ? (const T*)XV.col(pcol) : nullptr;
+  T xo = 0, xp = 0;
+  int64_t ro = 0;
+  if (r < n) {
+    ro = XV.row_off(r);
+    xo = x[ro];
+    if (xprev != nullptr) xp = xprev[ro];
+  }
+  const T sum = sell_row_dot<T, IDX>(ptr, width, col, kbase, val, XV, x,
+                                     nslices, s, lane);
+  if (r < n)
+    XV.col(ycol)[ro] = mpk_row<T>(sum, xo, xp, xprev != nullptr, rec, jrec);
 }
 
 inline unsigned spmv_grid(const Sell& S) {
@@ -208,6 +280,95 @@ void spmv_mpk(const Sell& S, const T* val, QView<T> Q, int jx, int jprev,
 #undef SGM_SPMV
   SGM_CHECK_LAUNCH();
 }
+
+// Depth-k matrix powers kernel (temporal blocking).  The rows are cut into
+// slabs of at least the matrix bandwidth h (|column - row| <= h), so step
+// j on slab S reads step j - 1's vector only on slabs S - 1 .. S + 1.
+// Launch L runs step j on slab L - 2 j for every step j of the group that
+// has such a slab: each piece then depends only on pieces of earlier
+// launches (step j - 1 on slabs up to S + 1 ran in launch S + 1 + 2 (j - 1)
+// = L - 1), and a slab's matrix rows are read again two launches after
+// their previous use, while still in the caches.  Rows are computed
+// exactly as by the one-step kernel.
+MpkPlan mpk_plan(const Sell& S, int64_t bandwidth, int depth, int vbytes) {
+  MpkPlan p;
+  p.depth = depth < 1 ? 1 : (depth > kMaxMpkTasks ? kMaxMpkTasks : depth);
+  if (p.depth == 1 || S.nslices < 1) {
+    p.depth = 1;
+    return p;
+  }
+  // slab: at least the bandwidth, at least 1024 slices (a launch of four
+  // pieces then has about 1000 workgroups), about 8 MB of matrix values and
+  // indices (two launches' worth of slabs then stay in the 256 MB Infinity
+  // Cache between a slab's uses)
+  const int64_t per_slice =
+      ceil_div(S.nnz_padded, S.nslices) * (vbytes + (S.rcol ? 2 : 4));
+  int64_t ns = ceil_div(bandwidth + 1, kSlice);
+  int64_t target = ((int64_t)8 << 20) / (per_slice > 0 ? per_slice : 1);
+  if (target < 1024) target = 1024;
+  if (ns < target) ns = target;
+  ns = round_up(ns, kSlicesPerBlock);
+  const int64_t G = ceil_div(S.nslices, ns);
+  if (G < 3) {
+    p.depth = 1;  // too few slabs to overlap
+    return p;
+  }
+  p.slab_slices = ns;
+  p.nslabs = G;
+  return p;
+}
+
+template <typename T>
+void spmv_mpk_steps(const Sell& S, const T* val, QView<T> Q,
+                    const MpkStep* steps, int nsteps, const double* rec,
+                    const MpkPlan& plan, hipStream_t st) {
+  if (nsteps <= 0) return;
+  if (plan.depth <= 1) {
+    for (int j = 0; j < nsteps; ++j)
+      spmv_mpk<T>(S, val, Q, steps[j].xcol, steps[j].pcol, steps[j].ycol, rec,
+                  steps[j].j, st);
+    return;
+  }
+  const int64_t G = plan.nslabs, ns = plan.slab_slices;
+  for (int j0 = 0; j0 < nsteps; j0 += plan.depth) {
+    const int k = nsteps - j0 < plan.depth ? nsteps - j0 : plan.depth;
+    for (int64_t L = 0; L < G + 2 * (k - 1); ++L) {
+      MpkTasks tasks;
+      tasks.count = 0;
+      int wg = 0;
+      for (int jj = k - 1; jj >= 0; --jj) {  // oldest step first
+        const int64_t slab = L - 2 * jj;
+        if (slab < 0 || slab >= G) continue;
+        MpkTask& t = tasks.t[tasks.count];
+        t.s0 = slab * ns;
+        t.ns = (slab + 1) * ns <= S.nslices ? ns : S.nslices - slab * ns;
+        t.xcol = steps[j0 + jj].xcol;
+        t.pcol = steps[j0 + jj].pcol;
+        t.ycol = steps[j0 + jj].ycol;
+        t.j = steps[j0 + jj].j;
+        tasks.wg[tasks.count] = wg;
+        wg += (int)round_up(ceil_div(t.ns, kSlicesPerBlock), 8);
+        ++tasks.count;
+      }
+      for (int u = tasks.count; u <= kMaxMpkTasks; ++u) tasks.wg[u] = wg;
+#define SGM_MPKT(IDX, colp)                                                   \
+  hipLaunchKernelGGL((k_mpk_tasks<T, IDX>), dim3((unsigned)wg),               \
+                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, S.kbase,  \
+                     val, Q, S.n, S.nslices, rec, tasks)
+      if (S.rcol) SGM_MPKT(int16_t, S.rcol); else SGM_MPKT(int32_t, S.col);
+#undef SGM_MPKT
+      SGM_CHECK_LAUNCH();
+    }
+  }
+}
+
+template void spmv_mpk_steps<double>(const Sell&, const double*,
+                                     QView<double>, const MpkStep*, int,
+                                     const double*, const MpkPlan&,
+                                     hipStream_t);
+template void spmv_mpk_steps<float>(const Sell&, const float*, QView<float>,
+                                    const MpkStep*, int, const double*,
+                                    const MpkPlan&, hipStream_t);
 
 int64_t resid_partials(const Sell& S) { return spmv_grid(S); }
 
