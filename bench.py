@@ -253,6 +253,8 @@ def study(args, np, torch, sgm, W):
     log(f"[bench] building {name}")
     if name == "banded_1m":
         return study_adjoint(args, np, torch, sgm, W)
+    if name == "aniso2d_4096" and args.to_tol:
+        return study_to_tol(args, np, torch, sgm, W)
     if name == "varcd3d_192":
         A = W.var_conv_diff_3d(192, 3)
         b_host = W.rhs(A.n, 3)
@@ -272,7 +274,7 @@ def study(args, np, torch, sgm, W):
     else:  # aniso2d_4096 (or --grid N: the same matrix family on N^2)
         grid = args.grid or 4096
         cyc = args.max_cycles or 5
-        A = W.aniso_diffusion_2d(grid)
+        A = W.aniso_diffusion_2d(grid, angle_deg=args.angle)
         b_host = W.rhs(A.n, 5)
         base = dict(s_max=200, restart=400, tol=1e-10, max_restarts=cyc - 1)
         b32 = dict(base, precision="fp32_ir", inner_tol=1e-6, max_outer=cyc,
@@ -285,7 +287,9 @@ def study(args, np, torch, sgm, W):
                   dict(b32, prephase="monomial", use_estimator=False))]
         cfg = {"workload": f"aniso2d_{grid}",
                "matrix": f"2D anisotropic diffusion 5-point {grid}^2, "
-                         "K = R(30deg) diag(1, 1e-3) R^T, K_xy dropped",
+                         f"K = R({args.angle:g}deg) diag(1, 1e-3) R^T, "
+                         f"K_xy dropped (axis ratio Kyy/Kxx = "
+                         f"{aniso_axis_ratio(args.angle):.4g})",
                "precond": "none", "s_max": 200, "restart": 400,
                "caps": f"float64: {cyc} restart cycles; float32-IR: {cyc} "
                        "outer steps",
@@ -357,6 +361,101 @@ def study(args, np, torch, sgm, W):
             "forward_ms": round((t1 - t0) * 1e3, 1),
             "backward_ms": round((t2 - t1) * 1e3, 1),
             "grad_b_finite": bool(torch.isfinite(bt.grad).all().item())}
+    out["cpu_baseline"] = None
+    return out
+
+
+def aniso_axis_ratio(angle_deg, ratio=1e-3):
+    """K_yy / K_xx of R(angle) diag(1, ratio) R^T: the anisotropy the 5-point
+    stencil keeps once K_xy is dropped."""
+    import math
+    a = math.radians(angle_deg)
+    kxx = math.cos(a) ** 2 + ratio * math.sin(a) ** 2
+    kyy = math.sin(a) ** 2 + ratio * math.cos(a) ** 2
+    return kyy / kxx
+
+
+def study_to_tol(args, np, torch, sgm, W):
+    """aniso2d_4096 solved to ||b - A x|| / ||b|| <= 1e-10.  A single solve
+    runs for minutes, so each mode runs as successive solves of
+    --chunk-cycles restart cycles (float64) or outer steps (float32-IR),
+    each from the previous iterate with its tolerance rescaled to ||b|| (the
+    product of the solves' reported residual ratios); each such solve
+    computes its own Ritz values and initial step size.  Float32-IR modes
+    also run the backward solve for L = 0.5 ||x||^2 (A^T lambda = x, the
+    gradient w.r.t. b), chunked the same way.  The final residuals are
+    checked on the host (scipy CSR product)."""
+    import scipy.sparse as sps
+    grid = args.grid or 4096
+    A = W.aniso_diffusion_2d(grid, angle_deg=args.angle)
+    b_host = W.rhs(A.n, 5)
+    M = sps.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n))
+    G = sgm.Matrix.from_csr(A)
+    tol = 1e-10
+    base = dict(s_max=200, restart=400)
+    b32 = dict(base, precision="fp32_ir", inner_tol=1e-6)
+    all_modes = {
+        "fp64": base,
+        "fp64_monomial_prephase": dict(base, prephase="monomial"),
+        "fp32_ir": b32,
+        "fp32_ir_monomial_no_estimator": dict(b32, prephase="monomial",
+                                              use_estimator=False)}
+    names = args.to_tol_modes.split(",")
+    C = args.chunk_cycles
+    ws = sgm.Workspace()
+
+    def chunked(rhs_host, o, label, transpose=False):
+        rhs = torch.tensor(rhs_host, device="cuda")
+        xa = torch.zeros_like(rhs)
+        xb = torch.empty_like(rhs)
+        rho, ms, iters, chunks, s0s = 1.0, 0.0, 0, 0, []
+        cap = (dict(max_outer=C) if o.get("precision") == "fp32_ir"
+               else dict(max_restarts=C - 1))
+        while rho > tol and chunks < args.max_chunks:
+            t0 = time.perf_counter()
+            r = sgm.solve(G, rhs, x0=xa, out=xb, workspace=ws, tol=tol / rho,
+                          transpose=transpose, mpk_depth=args.mpk_depth,
+                          **dict(o, **cap))
+            torch.cuda.synchronize()
+            ms += (time.perf_counter() - t0) * 1e3
+            rho *= r.info["rel_res_true"]
+            iters += r.info["iters"]
+            chunks += 1
+            s0s.append(r.info["s0_est"])
+            xa, xb = xb, xa
+            log(f"[bench] to-tol {label} chunk {chunks}: {ms / 1e3:.1f} s, "
+                f"{iters} iterations, rel {rho:.3e}")
+        xh = xa.cpu().numpy()
+        Mt = M.T.tocsr() if transpose else M
+        true = float(np.linalg.norm(rhs_host - Mt @ xh) /
+                     np.linalg.norm(rhs_host))
+        return xh, {"ms": round(ms, 1), "iters": iters, "chunks": chunks,
+                    "converged": bool(true <= tol * 1.0001),
+                    "rel_res_true_host": true, "s0_est_per_chunk": s0s}
+
+    out = {"metric": METRIC, "unit": "ms", "n_gpus": 1, "steps": 1,
+           "warmup": 0, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic",
+           "config": {"workload": f"aniso2d_{grid}_to_tol",
+                      "matrix": f"2D anisotropic diffusion 5-point {grid}^2,"
+                                f" K = R({args.angle:g}deg) diag(1, 1e-3) R^T"
+                                f" with K_xy dropped (axis ratio Kyy/Kxx = "
+                                f"{aniso_axis_ratio(args.angle):.4g})",
+                      "n": A.n, "nnz": A.nnz, "s_max": 200, "restart": 400,
+                      "tol": tol, "rhs": "N(0,1) seed 5", "x0": "zero",
+                      "chunk": f"{C} restart cycles / outer steps per solve"}}
+    for mname in names:
+        x, summ = chunked(b_host, all_modes[mname], mname)
+        out[mname] = summ
+        if mname.startswith("fp32_ir"):
+            _, bw = chunked(x, all_modes[mname], mname + " backward",
+                            transpose=True)
+            out[mname]["backward"] = bw
+    prim = names[0]
+    out["value"] = out[prim]["ms"]
+    out["ms_per_step"] = out[prim]["ms"]
+    out["dtype"] = "f64" if prim.startswith("fp64") else "f32/f64"
+    out["roofline"] = None
     out["cpu_baseline"] = None
     return out
 
@@ -446,6 +545,18 @@ def main():
                     help="aniso2d_4096 only: restart cycles (float64) and "
                          "outer steps (float32-IR), default 5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--to-tol", action="store_true",
+                    help="aniso2d_4096: solve to 1e-10 in chunks of "
+                         "--chunk-cycles cycles (see study_to_tol)")
+    ap.add_argument("--to-tol-modes", default="fp64",
+                    help="comma-separated: fp64, fp64_monomial_prephase, "
+                         "fp32_ir, fp32_ir_monomial_no_estimator")
+    ap.add_argument("--chunk-cycles", type=int, default=40)
+    ap.add_argument("--angle", type=float, default=30.0,
+                    help="aniso2d_4096: rotation of the diffusion tensor in "
+                         "degrees (30: axis ratio 0.334 after dropping K_xy;"
+                         " 0: the axis-aligned ratio 1e-3)")
+    ap.add_argument("--max-chunks", type=int, default=40)
     ap.add_argument("--mpk-depth", type=int, default=1,
                     help="matrix powers steps per pass over the matrix "
                          "(temporal blocking, 1-4) for every mode")

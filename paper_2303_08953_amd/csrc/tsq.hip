@@ -353,6 +353,8 @@ __global__ __launch_bounds__(kWBlock) void k_gemm_tn_wide(
     lstore(0);
   }
   __syncthreads();
+  // (a ring of three register stages, as in the wide Gram below, measured
+  // slower here: 41.8 against 40.2 ms at 201 x 200 over 16.8M rows)
   for (int64_t bt = bt0; bt < bt1; ++bt) {
     const bool more = bt + 1 < bt1;
     if (more) gload(bt + 1);
@@ -380,6 +382,157 @@ __global__ __launch_bounds__(kWBlock) void k_gemm_tn_wide(
       if (row < ma && col < nb)
         out[(int64_t)col * ma + row] = col < nbe ? (double)acc[i][r] : 0.0;
     }
+}
+
+// ------------------------------------------------------------- wide Gram
+// G = Q(:, b0:b0+nb)^T Q(:, b0:b0+nb) for Gram matrices of 65 to 256
+// columns.  One 512-thread workgroup per row chunk loads each 16-row batch
+// of all nb columns into LDS once (double-buffered, column stride 17), and
+// the eight wavefronts form the nt (nt + 1) / 2 tiles on and above the
+// diagonal (nt = 16 ceil(nb / 16)) from there: wavefront w takes the
+// contiguous run [T w / 8, T (w + 1) / 8) of them in column order, so
+// consecutive tiles mostly share their B operand, which is read once per
+// column.  The reduction mirrors the lower tiles.  Columns past nb read a
+// valid column (their results are not stored); columns past *ncount give
+// zero (as in the kernels above).  Grid: chunks workgroups, each a
+// contiguous range of batches.
+constexpr int kGTiles = 17;  // most tiles per wavefront (136 / 8 at nb = 256)
+constexpr int kGMaxCols = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kWBlock) void k_gram_wide(
+    QView<const T> Q, int b0c, int nb, const int* __restrict__ ncount,
+    int64_t nbatches, int chunks, double* __restrict__ part) {
+  typedef typename Vec4<T>::type V;
+  constexpr int EPV = 16 / (int)sizeof(T);  // elements per 16-byte load
+  constexpr int VPC = 16 / EPV;             // loads per 16-row column batch
+  constexpr int NVT = (kGMaxCols * VPC + kWBlock - 1) / kWBlock;
+  typedef T vec_t __attribute__((ext_vector_type(EPV)));
+  extern __shared__ char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int g = lane / 16, c16 = lane % 16;
+  const int nt = (nb + 15) / 16;
+  const int ncols = nt * 16;
+  const int NV = ncols * VPC;               // loads per batch
+  const int LBUF = ncols * kWStride;        // elements per LDS buffer
+  const int nbe = ncount ? min(nb, *ncount) : nb;
+  const int chunk = blockIdx.x;
+  const int64_t bt0 = nbatches * chunk / chunks;
+  const int64_t bt1 = nbatches * (chunk + 1) / chunks;
+  // this wavefront's tiles (row tile, column tile), column-major order of
+  // the upper triangle (wavefront-uniform)
+  const int T_all = nt * (nt + 1) / 2;
+  const int t0 = T_all * wave / 8, t1 = T_all * (wave + 1) / 8;
+  int tr[kGTiles], tc[kGTiles];
+  {
+    int c = 0, base = 0;  // tiles of columns < c: base = c (c + 1) / 2
+    while (base + c + 1 <= t0) {
+      base += c + 1;
+      ++c;
+    }
+    int r = t0 - base;
+#pragma unroll
+    for (int u = 0; u < kGTiles; ++u) {
+      tr[u] = r;
+      tc[u] = c;
+      if (++r > c) {
+        ++c;
+        r = 0;
+      }
+    }
+  }
+  const int cnt = t1 - t0;
+
+  // three register stages in a ring: the loads of batch b + 1 go out two
+  // batches before b + 1 is stored to LDS, so their latency is covered by
+  // the MFMA work of two batches
+  vec_t sA[NVT], sB[NVT], sC[NVT];
+  auto gload = [&](int64_t bt, vec_t (&stg)[NVT]) {
+    const T* rb = Q.base + Q.row_off(bt * 16);
+#pragma unroll
+    for (int q = 0; q < NVT; ++q) {
+      const int e = threadIdx.x + kWBlock * q;
+      if (e < NV) {
+        const int col = e / VPC;
+        const int c = b0c + (col < nb ? col : 0);
+        stg[q] = *reinterpret_cast<const vec_t*>(
+            rb + (int64_t)c * Q.cstride + (e % VPC) * EPV);
+      }
+    }
+  };
+  auto lstore = [&](int buf, const vec_t (&stg)[NVT]) {
+    T* L = lds + buf * LBUF;
+#pragma unroll
+    for (int q = 0; q < NVT; ++q) {
+      const int e = threadIdx.x + kWBlock * q;
+      if (e < NV) {
+        T* d = L + (e / VPC) * kWStride + (e % VPC) * EPV;
+#pragma unroll
+        for (int u = 0; u < EPV; ++u) d[u] = stg[q][u];
+      }
+    }
+  };
+
+  V acc[kGTiles];
+#pragma unroll
+  for (int u = 0; u < kGTiles; ++u) acc[u] = vzero<V>();
+  auto compute = [&](int buf) {
+    const T* L = lds + buf * LBUF + c16 * kWStride + g;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int cur = -1;
+      T bv = 0;
+#pragma unroll
+      for (int u = 0; u < kGTiles; ++u) {
+        if (u < cnt) {
+          if (tc[u] != cur) {
+            cur = tc[u];
+            bv = L[cur * 16 * kWStride + 4 * q];
+          }
+          acc[u] = mfma(L[tr[u] * 16 * kWStride + 4 * q], bv, acc[u]);
+        }
+      }
+    }
+  };
+  int buf = 0;
+  // batch b: compute from LDS, store batch b + 1 (registers `nxt`) to the
+  // other LDS buffer, load batch b + 3 into the registers `fre` that held b
+  auto step = [&](int64_t b, const vec_t (&nxt)[NVT], vec_t (&fre)[NVT]) {
+    if (b >= bt1) return;
+    compute(buf);
+    if (b + 1 < bt1) lstore(buf ^ 1, nxt);
+    if (b + 3 < bt1) gload(b + 3, fre);
+    __syncthreads();
+    buf ^= 1;
+  };
+  if (bt0 < bt1) {
+    gload(bt0, sA);
+    lstore(0, sA);
+  }
+  if (bt0 + 1 < bt1) gload(bt0 + 1, sB);
+  if (bt0 + 2 < bt1) gload(bt0 + 2, sC);
+  __syncthreads();
+  for (int64_t bt = bt0; bt < bt1; bt += 3) {
+    step(bt, sB, sA);
+    step(bt + 1, sC, sB);
+    step(bt + 2, sA, sC);
+  }
+  double* out = part + (int64_t)chunk * nb * nb;
+#pragma unroll
+  for (int u = 0; u < kGTiles; ++u) {
+    if (u < cnt) {
+      const int col = tc[u] * 16 + c16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = tr[u] * 16 + drow<T>(g, r);
+        if (row < nb && col < nb)
+          out[(int64_t)col * nb + row] =
+              (col < nbe && row < nbe) ? (double)acc[u][r] : 0.0;
+      }
+    }
+  }
 }
 
 // C(i, j) = sum over chunks of part[c][j * ma + i]; with sym, entries below
@@ -450,11 +603,17 @@ void launch_reduce(const double* part, int64_t nchunks, int ma, int nb,
 // threads, so the wavefronts of a CU share one staged copy.
 enum { MODE_UPDATE = 0, MODE_TRSM = 1 };
 
-template <typename T, int NT, int MT, int MODE, bool GRAM, int BLOCK = kBlock>
+// PACKED (MODE_TRSM only): M's upper triangle on the p accepted columns is
+// staged once per workgroup packed row by row (row k holds columns
+// k .. p-1 at k p - k (k - 1) / 2), so a triangular factor of up to 201
+// float64 columns fits in LDS whole instead of being re-staged in chunks
+// for every row block.
+template <typename T, int NT, int MT, int MODE, bool GRAM, int BLOCK = kBlock,
+          bool PACKED = false>
 __global__ __launch_bounds__(BLOCK) void k_update(
     QView<T> Q, int a0, int ka, int b0c, int nc,
     const double* __restrict__ M, int ldm, const int* __restrict__ ncount,
-    int64_t nrows, int kc, double* __restrict__ part) {
+    int64_t nrows, int kc, double* __restrict__ part, int nc_off = 0) {
   typedef typename Vec4<T>::type V;
   extern __shared__ char smem_raw[];
   T* Ms = reinterpret_cast<T*>(smem_raw);
@@ -463,16 +622,27 @@ __global__ __launch_bounds__(BLOCK) void k_update(
   const int lane = threadIdx.x % kWave;
   const int g = lane / 16, c16 = lane % 16;
   int nce = nc;
-  if (ncount) nce = min(nc, *ncount);
+  // a column group starting nc_off columns into the block keeps the
+  // block's accepted columns: *ncount - nc_off of its own
+  if (ncount) nce = max(0, min(nc, *ncount - nc_off));
   int kae = ka;
   if (MODE == MODE_TRSM) kae = nce;
   const int ka4 = (kae + 3) & ~3;
-  const bool single = ka4 <= kc;
+  const bool single = PACKED || ka4 <= kc;
   const int64_t rows_per_wave = 16 * MT;
   const int64_t rows_per_block = rows_per_wave * (BLOCK / kWave);
   const int64_t nblocks = (nrows + rows_per_block - 1) / rows_per_block;
 
   auto stage = [&](int k0) {
+    if constexpr (PACKED) {
+      for (int e = threadIdx.x; e < nce * nce; e += BLOCK) {
+        const int k = e / nce, c = e % nce;
+        if (c >= k)
+          Ms[k * nce - k * (k - 1) / 2 + (c - k)] =
+              (T)M[(int64_t)c * ldm + k];
+      }
+      return;
+    }
     for (int e = threadIdx.x; e < kc * W16; e += BLOCK) {
       const int kk = e / W16, cc = e % W16;
       const int k = k0 + kk;
@@ -530,10 +700,20 @@ __global__ __launch_bounds__(BLOCK) void k_update(
                         MT * c16;
         auto kstep = [&](int kk, const T (&a)[MT]) {
           const T* mrow = Ms + (kk + g) * W16 + c16;
+          // packed: row k of the triangle (zero left of the diagonal and
+          // past the accepted columns)
+          const int kp = k0 + kk + g;
+          const T* prow = Ms + (kp * nce - kp * (kp - 1) / 2) - kp;
 #pragma unroll
           for (int j = 0; j < NT; ++j) {
             if (MODE == MODE_TRSM && (k0 + kk) >= (j + 1) * 16) continue;
-            const T bv = mrow[j * 16];
+            T bv;
+            if constexpr (PACKED) {
+              const int c = j * 16 + c16;
+              bv = (c >= kp && c < nce && kp < nce) ? prow[c] : (T)0;
+            } else {
+              bv = mrow[j * 16];
+            }
 #pragma unroll
             for (int t = 0; t < MT; ++t) acc[t][j] = mfma(a[t], bv, acc[t][j]);
           }
@@ -1490,6 +1670,22 @@ void gemm_tn(QView<const T> Q, int a0, int ma, int b0, int nb,
     launch_reduce(P.buf, chunks_w, ma, nb, C, ldc, 0, st);
     return;
   }
+  // A Gram matrix of 129 to 256 columns: every 16-row batch of its columns
+  // in LDS once per workgroup, the tiles on and above the diagonal formed
+  // from there (the kernels below fetch each operand per wavefront).
+  // Measured in float64: 200 columns over 16.8M rows 20.2 against 33.6 ms;
+  // at 128 columns over 7.1M rows the kernel below is faster (4.2 against
+  // 4.7 ms), so it keeps those.
+  if (a0 == b0 && ma == nb && nb > 128 && nb <= kGMaxCols) {
+    const int chunks_g =
+        pick_chunks(2 * kNumCUs, 1, nbatches, (int64_t)nb * nb, P);
+    const size_t lds = (size_t)2 * nt_all * 16 * kWStride * sizeof(T);
+    hipLaunchKernelGGL(k_gram_wide<T>, dim3(chunks_g), dim3(kWBlock), lds,
+                       st, Q, b0, nb, ncount, nbatches, chunks_g, P.buf);
+    SGM_CHECK_LAUNCH();
+    launch_reduce(P.buf, chunks_g, nb, nb, C, ldc, 1, st);
+    return;
+  }
   // A float64 Gram matrix wider than 64 columns: 64 x 64 wave tiles, one
   // per wavefront, on and above the diagonal only.  (Measured at 128
   // columns over 7M rows: 4.1 ms against 4.5 ms for the full product in
@@ -1532,6 +1728,9 @@ constexpr int kLdsBudget = 64 * 1024;
 // (float64) or 300 (float32) at s = 128.
 constexpr int kWideLdsBudget = 152 * 1024;
 
+// Largest LDS of one workgroup on gfx950 (bytes).
+constexpr int kMaxLds = 160 * 1024;
+
 template <typename T, int NT, int MT, int MODE, bool GRAM, int BLOCK>
 void launch_update_b(QView<T> Q, int a0, int ka, int b0, int nc,
                      const double* M, int ldm, const int* ncount,
@@ -1541,6 +1740,23 @@ void launch_update_b(QView<T> Q, int a0, int ka, int b0, int nc,
   const int ka4 = (ka + 3) & ~3;
   int kc = lds_budget / (W16 * (int)sizeof(T));
   kc &= ~3;
+  if constexpr (MODE == MODE_TRSM && !GRAM && NT > 4 && sizeof(T) == 8) {
+    // a float64 triangular factor that does not fit whole: packed, when
+    // that fits (float32 factors fit whole up to 197 columns)
+    const size_t packed = (size_t)nc * (nc + 1) / 2 * sizeof(T);
+    if (kc < ka4 && packed <= (size_t)kMaxLds) {
+      const int64_t rows_per_block = 16 * MT * (BLOCK / kWave);
+      const int64_t nblocks = ceil_div(nrows, rows_per_block);
+      int64_t grid = nblocks < target_groups ? nblocks : target_groups;
+      if (grid < 1) grid = 1;
+      hipLaunchKernelGGL((k_update<T, NT, MT, MODE, false, BLOCK, true>),
+                         dim3((unsigned)grid), dim3(BLOCK), packed, st, Q, a0,
+                         ka, b0, nc, M, ldm, ncount, nrows, ka4,
+                         (double*)nullptr);
+      SGM_CHECK_LAUNCH();
+      return;
+    }
+  }
   if (kc > ka4) kc = ka4 < 4 ? 4 : ka4;
   size_t lds = (size_t)kc * W16 * sizeof(T);
   if (GRAM) {
@@ -1587,6 +1803,55 @@ void launch_update(QView<T> Q, int a0, int ka, int b0, int nc,
 
 }  // namespace
 
+// One column group of a wide update: 16 nt columns from column c0 of the
+// block (rows c0 .. of M), on the wide path (1,024 threads, the group's
+// slice of M staged whole in LDS).
+template <typename T, int NT>
+void launch_update_group(QView<T> Q, int a0, int ka, int b0, int c0, int ncg,
+                         const double* M, int ldm, const int* ncount,
+                         int64_t nrows, hipStream_t st) {
+  const int W16 = NT * 16;
+  const int ka4 = (ka + 3) & ~3;
+  const size_t lds = (size_t)ka4 * W16 * sizeof(T);
+  const int64_t rows_per_block = 16 * (1024 / kWave);
+  const int64_t nblocks = ceil_div(nrows, rows_per_block);
+  int64_t grid = nblocks < kNumCUs ? nblocks : kNumCUs;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((k_update<T, NT, 1, MODE_UPDATE, false, 1024>),
+                     dim3((unsigned)grid), dim3(1024), lds, st, Q, a0, ka,
+                     b0 + c0, ncg, M + (int64_t)c0 * ldm, ldm, ncount, nrows,
+                     ka4, (double*)nullptr, c0);
+  SGM_CHECK_LAUNCH();
+}
+
+// Column groups of at most 80 columns when the whole coefficient matrix M
+// (ka x nc) does not fit the wide kernel's LDS: each group's slice of M
+// then stays in LDS for the whole pass instead of being re-staged in
+// chunks for every row block.  The prior columns are read once per group.
+// Measured in float64 at ka = 201, nc = 200 over 16.8M rows (M 321 KB).
+template <typename T>
+bool update_in_groups(QView<T> Q, int a0, int ka, int b0, int nc,
+                      const double* M, int ldm, const int* ncount,
+                      int64_t nrows, hipStream_t st) {
+  const int ka4 = (ka + 3) & ~3;
+  const size_t whole = (size_t)ka4 * ((nc + 15) / 16) * 16 * sizeof(T);
+  if (whole <= (size_t)kWideLdsBudget) return false;
+  int wcols = (int)(kWideLdsBudget / ((size_t)ka4 * sizeof(T))) / 16 * 16;
+  if (wcols > 80) wcols = 80;
+  if (wcols < 16) return false;
+  for (int c0 = 0; c0 < nc; c0 += wcols) {
+    const int ncg = nc - c0 < wcols ? nc - c0 : wcols;
+    switch ((ncg + 15) / 16) {
+      case 1: launch_update_group<T, 1>(Q, a0, ka, b0, c0, ncg, M, ldm, ncount, nrows, st); break;
+      case 2: launch_update_group<T, 2>(Q, a0, ka, b0, c0, ncg, M, ldm, ncount, nrows, st); break;
+      case 3: launch_update_group<T, 3>(Q, a0, ka, b0, c0, ncg, M, ldm, ncount, nrows, st); break;
+      case 4: launch_update_group<T, 4>(Q, a0, ka, b0, c0, ncg, M, ldm, ncount, nrows, st); break;
+      default: launch_update_group<T, 5>(Q, a0, ka, b0, c0, ncg, M, ldm, ncount, nrows, st); break;
+    }
+  }
+  return true;
+}
+
 template <typename T>
 void update_gram(QView<T> Q, int a0, int ka, int b0, int nc, const double* M,
                  int ldm, const int* ncount, int64_t nrows, double* G,
@@ -1594,6 +1859,13 @@ void update_gram(QView<T> Q, int a0, int ka, int b0, int nc, const double* M,
   if (nc <= 0) return;
   const int nt = (nc + 15) / 16;
   const bool fuse = G != nullptr && nt <= 4;
+  if (!fuse && nt > 4 &&
+      update_in_groups<T>(Q, a0, ka, b0, nc, M, ldm, ncount, nrows, st)) {
+    if (G != nullptr)
+      gemm_tn<T>(Q.template as<const T>(), b0, nc, b0, nc, ncount, nrows, G,
+                 ldg, P, st);
+    return;
+  }
 #define SGM_UP(NTv, MTv)                                                      \
   if (nt == NTv) {                                                            \
     if (fuse)                                                                 \

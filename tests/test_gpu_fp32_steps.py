@@ -65,10 +65,13 @@ def _random_block(n, i, s, seed):
 
 
 @pytest.mark.parametrize("i,s", [(1, 8), (33, 32), (97, 32), (129, 128),
-                                 (7, 200)])
+                                 (7, 200), (201, 200)])
 def test_block_orth_classical_fp32(lib, i, s):
     """Full-rank blocks (kappa about 1.4): p = s on both sides; the new
-    basis vectors, R(1:i, k) and R(k, k) agree to float32 accuracy."""
+    basis vectors, R(1:i, k) and R(k, k) agree to float32 accuracy.
+    (201, 200) updates in column groups (its 201 x 200 coefficient matrix
+    does not fit in LDS whole) and forms its Gram with the LDS-shared
+    kernel."""
     n = 9001   # ragged last panel
     Qi, V = _random_block(n, i, s, seed=500 + i + s)
     p, Rt, Rk, Qg, ref = _run_fp32_block(lib, Qi, V)
