@@ -447,7 +447,7 @@ def study_to_tol(args, np, torch, sgm, W):
     for mname in names:
         x, summ = chunked(b_host, all_modes[mname], mname)
         out[mname] = summ
-        if mname.startswith("fp32_ir"):
+        if mname.startswith("fp32_ir") and not args.no_backward:
             _, bw = chunked(x, all_modes[mname], mname + " backward",
                             transpose=True)
             out[mname]["backward"] = bw
@@ -552,6 +552,8 @@ def main():
                     help="comma-separated: fp64, fp64_monomial_prephase, "
                          "fp32_ir, fp32_ir_monomial_no_estimator")
     ap.add_argument("--chunk-cycles", type=int, default=40)
+    ap.add_argument("--no-backward", action="store_true",
+                    help="--to-tol: skip the float32-IR backward solve")
     ap.add_argument("--angle", type=float, default=30.0,
                     help="aniso2d_4096: rotation of the diffusion tensor in "
                          "degrees (30: axis ratio 0.334 after dropping K_xy;"
