@@ -71,6 +71,74 @@ def jacobi_column_scaled(A):
     return (A @ sp.diags(1.0 / d)).tocsr(), d
 
 
+class ILU0:
+    """Incomplete LU factorisation with zero fill-in, ILU(0), as the right
+    preconditioner M = L U of the 2D Laplace test with an ILU preconditioner
+    (Sec. 4.3).  The paper names ILU(0) without defining it; this is the
+    textbook definition (Saad, Iterative Methods for Sparse Linear Systems,
+    Sec. 10.3): Gaussian elimination in row order (the IKJ form) in which
+    every update that would fall outside the sparsity pattern of A is
+    dropped.  L is unit lower triangular and U upper triangular, both on the
+    pattern of A, and (L U)_ij = a_ij at every nonzero (i, j) of A.
+
+    Needs every diagonal entry in the pattern and nonzero pivots.
+    solve(v) returns M^{-1} v by a forward and a backward triangular solve.
+    Each is one library step: SuperLU's factorisation of the triangular
+    factor in its natural order with the diagonal as pivot (which leaves it
+    as it is: L = L I, U = I U) followed by its solve, i.e. substitution
+    with the factor; factoring once keeps the many solves cheap."""
+
+    def __init__(self, A):
+        A = sp.csr_matrix(A, dtype=np.float64, copy=True)
+        A.sum_duplicates()
+        A.sort_indices()
+        n = A.shape[0]
+        rp, ci = A.indptr, A.indices
+        v = A.data
+        dpos = np.full(n, -1, dtype=np.int64)
+        for i in range(n):
+            for e in range(rp[i], rp[i + 1]):
+                if ci[e] == i:
+                    dpos[i] = e
+        if np.any(dpos < 0):
+            raise ValueError("ILU(0) needs every diagonal entry in the pattern")
+        for i in range(n):
+            where = {int(ci[e]): e for e in range(rp[i], rp[i + 1])}
+            # eliminate with the earlier rows k < i of row i's pattern, in
+            # increasing k; updates of later entries of row i (including
+            # its own lower ones, used further along this loop) stay in the
+            # pattern, the rest are dropped
+            for e in range(rp[i], dpos[i]):
+                k = int(ci[e])
+                piv = v[dpos[k]]
+                if piv == 0.0 or not np.isfinite(piv):
+                    raise ValueError(f"ILU(0): zero pivot in row {k}")
+                v[e] = v[e] / piv
+                for f in range(dpos[k] + 1, rp[k + 1]):
+                    t = where.get(int(ci[f]))
+                    if t is not None:
+                        v[t] -= v[e] * v[f]
+            if v[dpos[i]] == 0.0:
+                raise ValueError(f"ILU(0): zero pivot in row {i}")
+        F = sp.csr_matrix((v, ci, rp), shape=(n, n))
+        self.L = (sp.tril(F, k=-1) + sp.eye(n)).tocsr()
+        self.U = sp.triu(F).tocsr()
+        self.n = n
+        from scipy.sparse.linalg import splu
+        kw = dict(permc_spec="NATURAL", diag_pivot_thresh=0.0)
+        self._Ls = splu(self.L.tocsc(), **kw)
+        self._Us = splu(self.U.tocsc(), **kw)
+        for f in (self._Ls, self._Us):
+            if (np.any(f.perm_r != np.arange(n))
+                    or np.any(f.perm_c != np.arange(n))):
+                raise RuntimeError("triangular factor was reordered")
+
+    def solve(self, r):
+        """M^{-1} r = U^{-1} (L^{-1} r)."""
+        y = self._Ls.solve(np.asarray(r, dtype=np.float64))
+        return self._Us.solve(y)
+
+
 # ---------------------------------------------------------------------------
 # Shifts: Leja ordering, scaled Newton coefficients, change-of-basis matrix
 # ---------------------------------------------------------------------------
@@ -509,7 +577,7 @@ class Options:
     max_restarts: int = 1000
     tol: float = 1e-10
     basis: str = "scaled_newton"      # "scaled_newton" | "newton" | "monomial"
-    precond: str = "none"             # "none" | "jacobi"
+    precond: str = "none"             # "none" | "jacobi" | "ilu0"
     omega: float = 0.0                # 0 => 0.1 u^{-1/2} of the work precision
     omega_est: float = 0.0            # 0 => same rule
     use_estimator: bool = True
@@ -553,10 +621,13 @@ class _State:
 class _Engine:
     """Adaptive s-step GMRES cycles on one fixed (possibly scaled) matrix."""
 
-    def __init__(self, A, opts: Options):
+    def __init__(self, A, opts: Options, prec=None):
         self.A64 = A.astype(np.float64)
         self.wd = np.dtype(opts.work_dtype)
         self.Aw = A.astype(self.wd)
+        self.prec = prec        # right preconditioner (M^{-1} by .solve)
+        if prec is not None and self.wd != np.float64:
+            raise ValueError("the ILU(0) preconditioner is float64 only")
         self.o = opts
         self.u = U32 if self.wd == np.float32 else U64
         self.omega = opts.omega if opts.omega > 0 else default_omega(self.u)
@@ -574,7 +645,9 @@ class _Engine:
         V[:, 0] = q
         for j in range(s_eff):
             th, ga, de = shifts.record(j)
-            w = self.Aw @ V[:, j] - wt(th) * V[:, j]
+            # with a right preconditioner the Krylov operator is A M^{-1}
+            z = V[:, j] if self.prec is None else self.prec.solve(V[:, j])
+            w = self.Aw @ z - wt(th) * V[:, j]
             if j >= 1 and de != 0.0:
                 w = w - wt(de) * V[:, j - 1]
             V[:, j + 1] = w / wt(ga)
@@ -707,10 +780,15 @@ def solve(A, b, x0=None, opts: Options | None = None) -> Result:
     inside a cycle; the shifts are computed once per solve; with ritz_reuse
     the pre-phase columns are the first iterations of the first cycle.
     Right Jacobi preconditioning is column scaling (opts.precond="jacobi").
+    Right ILU(0) preconditioning (opts.precond="ilu0") runs the cycles on
+    A M^{-1} with M = L U and updates x += M^{-1} Q y, so the residuals are
+    those of A x = b.
     """
     o = opts or Options()
     if o.orth not in ("bcgs2", "bcgs2_pyth"):
         raise ValueError(f"unknown orth {o.orth!r}")
+    if o.precond not in ("none", "jacobi", "ilu0"):
+        raise ValueError(f"unknown preconditioner {o.precond!r}")
     A = A.tocsr().astype(np.float64)
     n = A.shape[0]
     b = np.asarray(b, dtype=np.float64)
@@ -719,7 +797,8 @@ def solve(A, b, x0=None, opts: Options | None = None) -> Result:
     if o.precond == "jacobi":
         A, dscale = jacobi_column_scaled(A)
         x = x * dscale                               # u0 = D x0
-    eng = _Engine(A, o)
+    prec = ILU0(A) if o.precond == "ilu0" else None
+    eng = _Engine(A, o, prec)
     r = b - eng.A64 @ x
     beta0 = float(np.linalg.norm(r))
     res_hist, s_hist, blocks, trueres = [], [], [], []
@@ -754,7 +833,7 @@ def solve(A, b, x0=None, opts: Options | None = None) -> Result:
         eng.cycle(Q, r, beta, beta0, st, logs, -1, prephase_only=True)
     while True:
         dx, k, _ = eng.cycle(Q, r, beta, beta0, st, logs, restarts)
-        x = x + dx
+        x = x + (dx if prec is None else prec.solve(dx))
         iters += k
         r = b - eng.A64 @ x
         beta = float(np.linalg.norm(r))
@@ -807,6 +886,8 @@ def solve_ir(A, b, x0=None, opts: Options | None = None, inner_tol=1e-4,
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros(n) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
     dscale = None
+    if o.precond == "ilu0":
+        raise ValueError("the ILU(0) preconditioner is float64 only")
     if o.precond == "jacobi":
         A, dscale = jacobi_column_scaled(A)
         x = x * dscale

@@ -123,6 +123,26 @@ CASES = [
      "self.wd = np.dtype(opts.work_dtype)",
      "self.wd = np.dtype(np.float64)",
      [(P.test_fp32_inner_cycle_is_the_gmres_minimiser, ())]),
+    ("ilu0_no_division_by_pivot",
+     "v[e] = v[e] / piv",
+     "v[e] = v[e]",
+     [(P.test_ilu0_reproduces_A_on_its_pattern, ("laplace2d_12",)),
+      (P.test_ilu0_five_point_closed_form, ())]),
+    ("ilu0_eliminates_with_the_lower_part",
+     "for f in range(dpos[k] + 1, rp[k + 1]):",
+     "for f in range(rp[k], dpos[k]):",
+     [(P.test_ilu0_reproduces_A_on_its_pattern, ("random_90",)),
+      (P.test_ilu0_of_tridiagonal_is_the_exact_lu, ())]),
+    ("ilu0_update_without_preconditioner",
+     "x = x + (dx if prec is None else prec.solve(dx))",
+     "x = x + dx",
+     [(P.test_ilu0_right_preconditioned_iterates_are_gmres_minimisers,
+       ("scaled_newton",))]),
+    ("ilu0_shift_on_the_preconditioned_vector",
+     "w = self.Aw @ z - wt(th) * V[:, j]",
+     "w = self.Aw @ z - wt(th) * z",
+     [(P.test_ilu0_right_preconditioned_iterates_are_gmres_minimisers,
+       ("scaled_newton",))]),
     ("givens_rhs_not_rotated",
      "self.g[col + 1] = -ss * gc",
      "self.g[col + 1] = ss * gc",

@@ -780,3 +780,135 @@ def test_pythagorean_solves_keep_the_pins():
     assert ra.status == rb.status == "ok"
     assert ra.s_hist == rb.s_hist
     assert np.linalg.norm(ra.x - rb.x) <= 1e-9 * np.linalg.norm(ra.x)
+
+
+# ---------------------------------------------------------------- ILU(0) (f2)
+
+def _pattern_random(n=90, seed=11):
+    """Nonsymmetric sparse matrix with a full diagonal and a ragged pattern
+    (dominant diagonal, so ILU(0) has nonzero pivots)."""
+    rng = np.random.default_rng(seed)
+    A = sp.random(n, n, density=5.0 / n, random_state=rng, format="csr")
+    A = A - 0.5 * A.sign()
+    d = np.asarray(abs(A).sum(axis=1)).ravel() + 1.0
+    return (A + sp.diags(d)).tocsr()
+
+
+@pytest.mark.parametrize("which", ["laplace2d_12", "random_90"])
+def test_ilu0_reproduces_A_on_its_pattern(which):
+    """ILU(0)'s defining property (Saad, Sec. 10.3): L unit lower and U upper
+    triangular on the pattern of A, with (L U)_ij = a_ij at every nonzero
+    (i, j) of A.  Checked with a dense product."""
+    if which == "laplace2d_12":
+        M = csr(W.laplace_2d(12))
+    else:
+        M = _pattern_random()
+    f = o.ILU0(M)
+    Ad = M.toarray()
+    mask = Ad != 0
+    L, U = f.L.toarray(), f.U.toarray()
+    assert np.array_equal(np.diag(L), np.ones(M.shape[0]))
+    assert np.all(np.triu(L, 1) == 0) and np.all(np.tril(U, -1) == 0)
+    off = ~np.eye(M.shape[0], dtype=bool)
+    assert np.all(mask[(L != 0) & off]) and np.all(mask[U != 0])
+    LU = L @ U
+    assert np.abs(LU[mask] - Ad[mask]).max() <= 1e-13 * np.abs(Ad).max()
+    # fill-in outside the pattern is what ILU(0) drops: it is not zero here
+    assert np.abs(LU[~mask]).max() > 1e-3
+
+
+def test_ilu0_of_tridiagonal_is_the_exact_lu():
+    """A tridiagonal matrix has no fill, so ILU(0) is its exact LU
+    factorisation; with a column-dominant diagonal partial pivoting keeps
+    the identity permutation and scipy's dense LU gives the same factors."""
+    import scipy.linalg as sla
+    n = 40
+    rng = np.random.default_rng(2)
+    lo, up = rng.uniform(-1, 1, n - 1), rng.uniform(-1, 1, n - 1)
+    A = sp.diags([lo, 3.0 + rng.uniform(0, 1, n), up], [-1, 0, 1]).tocsr()
+    f = o.ILU0(A)
+    P_, L_, U_ = sla.lu(A.toarray())
+    assert np.array_equal(P_, np.eye(n))
+    assert np.allclose(f.L.toarray(), L_, rtol=0, atol=1e-14)
+    assert np.allclose(f.U.toarray(), U_, rtol=0, atol=1e-14)
+
+
+def test_ilu0_five_point_closed_form():
+    """ILU(0) of the 5-point Laplacian (4, -1) in natural ordering has the
+    classical closed form (Meijerink and van der Vorst): pivots
+    d_ij = 4 - 1/d_(i-1)j - 1/d_i(j-1), L entries -1/d of the west and
+    south neighbours, U off-diagonals -1."""
+    N = 15
+    M = csr(W.laplace_2d(N))
+    f = o.ILU0(M)
+    d = np.zeros((N, N))
+    for j in range(N):          # slow axis
+        for i in range(N):      # fast axis
+            v = 4.0
+            if i > 0:
+                v -= 1.0 / d[j, i - 1]
+            if j > 0:
+                v -= 1.0 / d[j - 1, i]
+            d[j, i] = v
+    dd = d.ravel()
+    U, L = f.U.toarray(), f.L.toarray()
+    assert np.allclose(np.diag(U), dd, rtol=1e-14)
+    r = np.arange(N * N)
+    west = r[(r % N) > 0]
+    south = r[r >= N]
+    assert np.allclose(L[west, west - 1], -1.0 / dd[west - 1], rtol=1e-14)
+    assert np.allclose(L[south, south - N], -1.0 / dd[south - N], rtol=1e-14)
+    assert np.all(U[west - 1, west] == -1.0) and np.all(U[south - N, south] == -1.0)
+
+
+@pytest.mark.parametrize("basis", ["monomial", "scaled_newton"])
+def test_ilu0_right_preconditioned_iterates_are_gmres_minimisers(basis):
+    """Right preconditioning: the cycles run on A M^{-1} (M = L U) and
+    x = x0 + M^{-1} u.  With fixed s the iterates are those of MGS-GMRES on
+    the dense operator A M^{-1} (P1 / P15 applied to it), and the converged
+    x solves A x = b."""
+    A = W.conv_diff_2d(16, 10.0)
+    M = csr(A)
+    b = W.rhs(A.n, 7)
+    f = o.ILU0(M)
+    Ad = M.toarray()
+    AMi = Ad @ np.linalg.inv((f.L @ f.U).toarray())
+    k = 8                       # residual still above 1e-9 (it converges fast)
+    r = o.solve(M, b, opts=o.Options(s_max=4, restart=k, max_restarts=0,
+                                     tol=1e-300, basis=basis,
+                                     use_estimator=False, precond="ilu0"))
+    _, hm, _ = o.mgs_gmres(sp.csr_matrix(AMi), b, restart=k, tol=1e-300,
+                           max_restarts=0)
+    assert len(r.res_hist) == k and min(hm) > 1e-9
+    assert np.allclose(r.res_hist, hm, rtol=1e-6, atol=0)
+    u = o.gmres_iterates_dense(AMi, b, np.zeros(A.n), k)
+    x = np.linalg.solve((f.L @ f.U).toarray(), u)
+    assert np.linalg.norm(r.x - x) <= 1e-8 * np.linalg.norm(x)
+    rc = o.solve(M, b, opts=o.Options(s_max=8, restart=32, tol=1e-12,
+                                      precond="ilu0"))
+    assert rc.status == "ok"
+    xs = np.linalg.solve(Ad, b)
+    assert np.linalg.norm(Ad @ rc.x - b) / np.linalg.norm(b) <= 1e-12
+    assert np.linalg.norm(rc.x - xs) <= np.linalg.cond(Ad) * 1e-11 * np.linalg.norm(xs)
+    r0 = o.solve(M, b, opts=o.Options(s_max=8, restart=32, tol=1e-12))
+    assert rc.iters < r0.iters
+
+
+@pytest.mark.slow
+def test_E6_laplace_ilu0_single_block():
+    """Sec. 4.3, 2D Laplace with an ILU preconditioner: the 400^2 matrix of
+    Test 2 with right ILU(0), s0 = 400, scaled Newton: the adapted step size
+    is 400 (one block of all 400 columns).  Ritz values from a separate
+    400-step pre-phase (as in Test 3), Omega = 1e7, m = 400; b as in the
+    Test 2 pin.  The block's residuals fall monotonically by ten orders."""
+    g = golden("paper_stability_results.json")["E6"]
+    A = W.laplace_2d(400)
+    b = W.rhs(A.n, 1)
+    r = o.solve(csr(A), b, opts=o.Options(
+        s_max=400, restart=400, max_restarts=0, tol=1e-300,
+        basis="scaled_newton", omega=1e7, use_estimator=False,
+        ritz_reuse=False, precond="ilu0"))
+    assert r.s_hist == [g["adapted_s_scaled_newton"]]
+    h = np.asarray(r.res_hist)
+    assert np.all(np.diff(h) <= 1e-12 * h[:-1])
+    assert h[-1] <= 1e-9 and r.rel_res_true <= 1e-9
