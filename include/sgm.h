@@ -16,8 +16,9 @@
  *    results (sgm_solve, sgm_block_orth, sgm_shifts) synchronise `stream`
  *    before returning; the others return after enqueueing.
  *  - The caller owns every buffer it passes.  The library allocates device
- *    memory only in sgm_matrix_create (the analysed copies of the matrix) and
- *    frees it in sgm_matrix_destroy.  Scratch for a solve is the caller's
+ *    memory only in sgm_matrix_create (the analysed copies of the matrix)
+ *    and sgm_matrix_ilu0 (its ILU(0) factors) and frees it in
+ *    sgm_matrix_destroy.  Scratch for a solve is the caller's
  *    workspace, sized by sgm_workspace_size.  The one exception is
  *    sgm_block_orth_noalloc, whose scratch is a static device array of the
  *    library (24 MiB per GPU, for the life of the process).
@@ -52,7 +53,14 @@ typedef enum {
   SGM_BASIS_MONOMIAL = 2       /* Eq. (monomial), p_j(A) = A^j               */
 } sgm_basis;
 
-typedef enum { SGM_PRECOND_NONE = 0, SGM_PRECOND_JACOBI = 1 } sgm_precond;
+typedef enum {
+  SGM_PRECOND_NONE = 0,
+  SGM_PRECOND_JACOBI = 1,  /* right Jacobi = column scaling A D^{-1}        */
+  SGM_PRECOND_ILU0 = 2     /* right ILU(0), M = L U (the preconditioner of
+                              the 2D Laplace test of Sec. 4.3); float64,
+                              forward solves only; the factors come from
+                              sgm_matrix_ilu0                              */
+} sgm_precond;
 
 typedef enum {
   SGM_PREPHASE_CGS2 = 0,     /* one column per step (column-wise Arnoldi)  */
@@ -97,6 +105,34 @@ sgm_status sgm_matrix_update_values(sgm_matrix A, const double* val,
 
 sgm_status sgm_matrix_destroy(sgm_matrix A);
 
+/* ILU(0) factors of A for right preconditioning (SGM_PRECOND_ILU0; the
+ * preconditioner of the 2D Laplace test with an ILU preconditioner, Sec.
+ * 4.3).  Zero fill-in: Gaussian elimination in row order that drops every
+ * update outside the pattern of A, so L (unit lower) and U (upper) have A's
+ * pattern and (L U)_ij = a_ij at every stored (i, j).  Everything runs on
+ * the GPU: the levels of the forward and backward substitutions (a row's
+ * level is one more than the highest among the rows it depends on), rows
+ * sorted by level, and the factorisation level by level.  Needs every
+ * diagonal entry stored and column indices sorted within each row
+ * (SGM_EINVAL otherwise); a zero or non-finite pivot gives SGM_ENUMERIC.
+ * The factors belong to the handle (device memory allocated here, freed by
+ * sgm_matrix_destroy or a later call) and are recomputed by
+ * sgm_matrix_update_values.  levels (host, 2 entries, may be NULL) receives
+ * the level counts of the forward and backward substitutions.
+ * Synchronises `stream`. */
+sgm_status sgm_matrix_ilu0(sgm_matrix A, void* stream, int32_t* levels);
+
+/* z = M^{-1} r = U^{-1} (L^{-1} r) with the ILU(0) factors: r, z double[n]
+ * (device, may alias).  One workgroup walks the levels of each
+ * substitution in order. */
+sgm_status sgm_ilu0_apply(sgm_matrix A, const double* r, double* z,
+                          void* stream);
+
+/* Copies the ILU(0) factors into lu[nnz] (device), in the CSR order of A:
+ * the multipliers of L at the strict lower entries, U on and above the
+ * diagonal. */
+sgm_status sgm_ilu0_factors(sgm_matrix A, double* lu, void* stream);
+
 /* Sizes of an analysed matrix (host outputs, each may be NULL): n, nnz,
  * the padded SELL-C-64 entry count of A, and index_bytes[2] = the bytes
  * per column index the SpMV of A and of A^T reads: 2 when every group of 64
@@ -119,7 +155,7 @@ typedef struct {
   int32_t restart;        /* m, basis vectors per cycle (Alg. 4); >= 1       */
   int32_t max_restarts;   /* restarts after the first cycle; >= 0            */
   double tol;             /* on ||b - A x|| / ||b - A x0|| (Sec. 4); > 0     */
-  sgm_precond precond;    /* right Jacobi = column scaling A D^{-1}          */
+  sgm_precond precond;    /* right preconditioner (see sgm_precond)         */
   sgm_basis basis;
   sgm_precision precision;
   double omega;           /* Alg. 3 bound; 0 => 0.1 u^{-1/2} of the Gram's

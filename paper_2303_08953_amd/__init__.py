@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libsgm.so")
 # status codes
 OK, NOT_CONVERGED, EINVAL, EHIP, ENOMEM, ENUMERIC = 0, 1, -1, -2, -3, -4
 BASIS = {"scaled_newton": 0, "newton": 1, "monomial": 2}
-PRECOND = {"none": 0, "jacobi": 1}
+PRECOND = {"none": 0, "jacobi": 1, "ilu0": 2}
 PRECISION = {"fp64": 0, "fp32_ir": 1}
 PREPHASE = {"cgs2": 0, "monomial": 1}
 ORTH = {"bcgs2": 0, "bcgs2_pyth": 1}
@@ -81,6 +81,9 @@ _SIGS = [
     ("sgm_matrix_info", C.c_int,
      [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
       C.POINTER(C.c_int32)]),
+    ("sgm_matrix_ilu0", C.c_int, [_P, _P, C.POINTER(C.c_int32)]),
+    ("sgm_ilu0_apply", C.c_int, [_P, _P, _P, _P]),
+    ("sgm_ilu0_factors", C.c_int, [_P, _P, _P]),
     ("sgm_spmv", C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P]),
     ("sgm_opts_default", None, [C.POINTER(Opts)]),
     ("sgm_workspace_size", C.c_int, [_P, C.POINTER(Opts), C.POINTER(C.c_size_t)]),
@@ -199,6 +202,30 @@ class Matrix:
                                               _stream(stream)))
         self.version += 1
 
+    def ilu0(self, stream=None):
+        """sgm_matrix_ilu0: ILU(0) factors for precond="ilu0"; returns the
+        level counts of the forward and backward substitutions."""
+        lv = (C.c_int32 * 2)()
+        _check(lib().sgm_matrix_ilu0(self._h, _stream(stream), lv))
+        self.ilu_levels = (lv[0], lv[1])
+        return self.ilu_levels
+
+    def ilu0_apply(self, r, out=None, stream=None):
+        """z = M^{-1} r with the ILU(0) factors (sgm_ilu0_apply)."""
+        torch = _torch()
+        r = _dev(r, torch.float64)
+        z = out if out is not None else torch.empty_like(r)
+        _check(lib().sgm_ilu0_apply(self._h, _ptr(r), _ptr(z),
+                                    _stream(stream)))
+        return z
+
+    def ilu0_factors(self, stream=None):
+        """The ILU(0) factor values in the CSR order of A (sgm_ilu0_factors)."""
+        torch = _torch()
+        lu = torch.empty(self.nnz, dtype=torch.float64, device="cuda")
+        _check(lib().sgm_ilu0_factors(self._h, _ptr(lu), _stream(stream)))
+        return lu
+
     def info(self):
         n, nnz, snnz = C.c_int64(), C.c_int64(), C.c_int64()
         ib = (C.c_int32 * 2)()
@@ -289,8 +316,12 @@ class SolveResult:
 
 def solve(A: Matrix, b, x0=None, out=None, workspace: Workspace | None = None,
           stream=None, hist_cap=200000, **opts) -> SolveResult:
-    """sgm_solve: adaptive s-step GMRES(m) on the GPU (Alg. 4)."""
+    """sgm_solve: adaptive s-step GMRES(m) on the GPU (Alg. 4).  With
+    precond="ilu0" the matrix's ILU(0) factors are built first if it has
+    none (sgm_matrix_ilu0)."""
     torch = _torch()
+    if opts.get("precond") == "ilu0" and getattr(A, "ilu_levels", None) is None:
+        A.ilu0(stream)
     o, keep = make_opts(**opts)
     nb = C.c_size_t()
     _check(lib().sgm_workspace_size(A.handle, C.byref(o), C.byref(nb)))

@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "libsgm.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["matrix.hip", "spmv.hip", "tsq.hip", "small.hip", "shifts.hip",
-           "solver.hip"]
+           "ilu.hip", "solver.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -126,6 +126,31 @@ struct Sell {
   float* val32 = nullptr;   // [nnz_padded]
 };
 
+// ILU(0) factors (right preconditioner M = L U, zero fill-in).  Each
+// substitution's rows are grouped by level (one more than the highest level
+// among the rows the row depends on) and sorted within a level; the strict
+// triangle of each position's row is stored in level order as ELL (entry t
+// of position p at t * n + p; cnt[p] entries).
+struct IluLevels {
+  int32_t nlev = 0;           // levels (host copy)
+  int32_t width = 0;          // largest row of the triangle (host copy)
+  int32_t* rows = nullptr;    // [n] rows in level order
+  int32_t* lptr = nullptr;    // [nlev + 1] first position of each level
+  int32_t* cnt = nullptr;     // [n]
+  int32_t* ecol = nullptr;    // [width * n]
+  int32_t* esrc = nullptr;    // [width * n] CSR index of the entry, -1 pad
+  double* eval = nullptr;     // [width * n] factor values
+};
+struct Ilu {
+  int32_t* dpos = nullptr;     // [n] CSR index of each diagonal entry
+  double* fac = nullptr;       // [nnz] L (strict lower) and U, CSR order
+  double* dinv = nullptr;      // [n] 1 / u_rr in backward-level order
+  int32_t* nlev_dev = nullptr; // [2] levels of the forward, backward side
+  int32_t* flags = nullptr;    // [4] analysis / pivot flags
+  IluLevels L, U;
+  bool ok = false;             // factors valid for the current values
+};
+
 struct Matrix {
   int64_t n = 0, nnz = 0;
   int32_t* row_ptr = nullptr;  // CSR copy (device)
@@ -136,6 +161,7 @@ struct Matrix {
   int64_t bandwidth = 0;       // max |column - row| over the nonzeros
   Sell fwd;                    // A
   Sell trn;                    // A^T
+  Ilu* ilu = nullptr;          // ILU(0) factors, built on request
   // Jacobi-scaled value copies (A D^{-1}), built on demand inside a solve's
   // workspace; nothing cached here.
 };
@@ -152,6 +178,17 @@ void sell_fill_values(const Sell& S, const double* csr_val, hipStream_t st);
 void sell_free(Sell& S);
 void matrix_extract_diag(Matrix& M, hipStream_t st);
 
+// ILU(0): analysis (diagonal positions, levels, level-ordered structure)
+// and factorisation; ilu_factor recomputes the factors from the current
+// values.  Both throw SGM_EINVAL (no stored diagonal, unsorted columns) or
+// SGM_ENUMERIC (zero or non-finite pivot).
+void ilu_build(Matrix& M, hipStream_t st);
+void ilu_factor(Matrix& M, hipStream_t st);
+void ilu_free(Ilu*& I);
+// z = M^{-1} b (float64), b read at BV.row_off(row); b may be z.
+void ilu_apply(const Ilu& I, int64_t n, QView<const double> BV,
+               const double* b, double* z, hipStream_t st);
+
 // ------------------------------------------------------------------ SpMV
 enum SpmvEpi { EPI_PLAIN = 0, EPI_MPK = 1, EPI_RESID = 2 };
 
@@ -165,6 +202,13 @@ void spmv_plain(const Sell& S, const T* val, const T* x, T* y,
 template <typename T>
 void spmv_mpk(const Sell& S, const T* val, QView<T> Q, int jx, int jprev,
               int jy, const double* rec, int j, hipStream_t st);
+// The same step with a right preconditioner: y = ((A z) - theta x -
+// delta xprev) / gamma, z = M^{-1} x given as a plain vector (float64).
+void spmv_mpk_prec(const Sell& S, const double* val, QView<double> Q,
+                   const double* z, int jx, int jprev, int jy,
+                   const double* rec, int j, hipStream_t st);
+// x(0:n) += z(0:n) (float64)
+void axpy_f64(const double* z, double* x, int64_t n, hipStream_t st);
 // Depth-k matrix powers kernel (temporal blocking over row slabs): the
 // steps j of one block, each y = column ycol from x = column xcol (and the
 // previous vector, column pcol, when pcol >= 0) with records rec[3 j..].

@@ -400,6 +400,8 @@ void matrix_update_values(Matrix* M, const double* val, hipStream_t st) {
   matrix_extract_diag(*M, st);
   sell_fill_values(M->fwd, M->val, st);
   sell_fill_values(M->trn, M->val, st);
+  // ILU(0) factors, when built, follow the values
+  if (M->ilu) ilu_factor(*M, st);
 }
 
 void matrix_destroy(Matrix* M) {
@@ -407,6 +409,7 @@ void matrix_destroy(Matrix* M) {
   (void)hipDeviceSynchronize();
   sell_free(M->fwd);
   sell_free(M->trn);
+  ilu_free(M->ilu);
   dfree(M->row_ptr); dfree(M->col); dfree(M->row_of); dfree(M->val);
   dfree(M->diag);
   delete M;

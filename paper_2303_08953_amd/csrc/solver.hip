@@ -38,6 +38,7 @@ struct Work {
   double* r = nullptr;
   double* jac64 = nullptr;
   float* jac32 = nullptr;
+  double* ilu_z = nullptr;  // M^{-1} of the current vector (ILU(0))
   Partials P;
   double *W = nullptr, *G = nullptr, *Z = nullptr, *Zinv = nullptr;
   double *R2 = nullptr, *G2 = nullptr, *Zt = nullptr, *Ztinv = nullptr;
@@ -83,7 +84,7 @@ int64_t part_cap(int m, int smax, int64_t n) {
 }
 
 void layout(Arena& a, Work& w, int64_t n, int64_t sell_nnz, int m, int smax,
-            int nshift_max, bool fp32, bool jacobi) {
+            int nshift_max, bool fp32, bool jacobi, bool ilu) {
   w.ld = round_up(n, kLdAlign);
   w.ldw = m + 1;
   w.lds = smax;
@@ -98,6 +99,7 @@ void layout(Arena& a, Work& w, int64_t n, int64_t sell_nnz, int m, int smax,
     w.jac64 = a.take<double>(sell_nnz);
     w.jac32 = a.take<float>(sell_nnz);
   }
+  if (ilu) w.ilu_z = a.take<double>(w.ld);
   w.P.cap = part_cap(m, smax, n);
   w.P.buf = a.take<double>(w.P.cap);
   const int64_t ws = (int64_t)w.ldw * smax, ss = (int64_t)smax * smax;
@@ -315,6 +317,7 @@ struct Engine {
   hipEvent_t ev[4];
   MpkPlan mplan;
   std::vector<MpkStep> msteps;
+  const Ilu* ilu = nullptr;  // right ILU(0) preconditioner (float64 only)
 
   Engine(const Matrix& A_, const Sell& S_, const T* v, const double* v64,
          Work& w_, HostMirror hm_, hipStream_t st_, const sgm_opts& o_,
@@ -407,6 +410,18 @@ struct Engine {
     int p2, ph, brk, kdone, conv, bad;
   };
 
+  // One matrix powers step with the right preconditioner: z = M^{-1} x,
+  // then y = ((A z) - theta x - delta xprev) / gamma.
+  void mpk_step_prec(const MpkStep& m, const double* rec) {
+    if constexpr (sizeof(T) == 8) {
+      const QView<double> Qd = Q();
+      ilu_apply(*ilu, n, Qd.template as<const double>(), Qd.col(m.xcol),
+                w.ilu_z, st);
+      spmv_mpk_prec(S, vals, Qd, w.ilu_z, m.xcol, m.pcol, m.ycol, rec, m.j,
+                    st);
+    }
+  }
+
   // One s-step block: MPK, BCGS2 + partial CholQR2, Hessenberg recovery,
   // Givens and the convergence test; one host synchronisation at the end.
   BlockOut block(int nb, int s_eff, bool mono, const double* beta0,
@@ -421,7 +436,11 @@ struct Engine {
       const int jprev = (j >= 1 && delta != 0.0) ? nb - 2 + j : -1;
       msteps[j] = MpkStep{nb - 1 + j, jprev, nb + j, q};
     }
-    spmv_mpk_steps<T>(S, vals, Q(), msteps.data(), s_eff, rec, mplan, st);
+    if (ilu != nullptr) {
+      for (int j = 0; j < s_eff; ++j) mpk_step_prec(msteps[j], rec);
+    } else {
+      spmv_mpk_steps<T>(S, vals, Q(), msteps.data(), s_eff, rec, mplan, st);
+    }
     SGM_HIP(hipEventRecord(ev[1], st));
     orth_block<T>(Q(), ld, nb, s_eff, omega, w, st, false,
                   o.orth == SGM_ORTH_BCGS2_PYTH);
@@ -465,7 +484,10 @@ struct Engine {
     if (t0 == 0) SGM_HIP(hipMemsetAsync(w.ctrl + C_STOP, 0, sizeof(int), st));
     for (int t = t0; t < t0 + nsteps; ++t) {
       const int nbt = 1 + t;
-      spmv_mpk<T>(S, vals, Q(), nbt - 1, -1, nbt, w.mono, 0, st);
+      if (ilu != nullptr)
+        mpk_step_prec(MpkStep{nbt - 1, -1, nbt, 0}, w.mono);
+      else
+        spmv_mpk<T>(S, vals, Q(), nbt - 1, -1, nbt, w.mono, 0, st);
       orth_block<T>(Q(), ld, nbt, 1, omega, w, st, false);
       block_tail(w.W, w.R2, w.ldw, w.Z, w.Zt, w.Zinv, w.Ztinv, w.lds, nbt,
                  w.ctrl, nullptr, nullptr, w.Hraw, w.Hr, w.ldh, w.cs, w.sn,
@@ -587,7 +609,11 @@ void run_solve(Handle* h, const double* b, const double* x0, double* x,
   const Sell& S = o.transpose ? A.trn : A.fwd;
   const int64_t n = A.n;
   const bool jac = o.precond == SGM_PRECOND_JACOBI;
+  const bool ilu = o.precond == SGM_PRECOND_ILU0;
   const bool f32 = sizeof(T) == 4;
+  if (ilu)
+    SGM_REQUIRE(A.ilu != nullptr && A.ilu->ok,
+                "no valid ILU(0) factors: call sgm_matrix_ilu0 first");
   auto t0 = Clock::now();
   HostMirror hm;
   hm.ctrl = static_cast<int*>(h->pinned);
@@ -625,6 +651,13 @@ void run_solve(Handle* h, const double* b, const double* x0, double* x,
   SGM_HIP(hipMemcpyAsync(w.scal + 2, &one, sizeof(double),
                          hipMemcpyHostToDevice, st));
   Engine<T> E(A, S, vT, v64, w, hm, st, o, R);
+  if (ilu) {
+    // one preconditioned step at a time (the fused kernel has no M^{-1})
+    E.ilu = A.ilu;
+    E.mplan = MpkPlan{};
+    R.mpk_depth = 1;
+    R.mpk_slab_rows = 0;
+  }
   E.set_monomial();
   if (o.basis == SGM_BASIS_MONOMIAL) {
     E.sh.known = true;
@@ -682,8 +715,18 @@ void run_solve(Handle* h, const double* b, const double* x0, double* x,
       scale_into<T>(w.r, w.scal + 1, E.Q(), 0, n, w.ld, st);
       const int k = E.cycle(w.scal + 1, w.scal + 0, o.tol, false, 1.0, nullptr);
       auto tc = Clock::now();
-      gemv_update<T>(E.Q().template as<const T>(), w.y, k, nullptr, x, n,
-                     st);
+      if (ilu) {
+        // right preconditioning: x += M^{-1} (Q y)
+        SGM_HIP(hipMemsetAsync(w.ilu_z, 0, sizeof(double) * n, st));
+        gemv_update<T>(E.Q().template as<const T>(), w.y, k, nullptr,
+                       w.ilu_z, n, st);
+        ilu_apply(*A.ilu, n, colmajor_view<const double>(w.ilu_z, w.ld),
+                  w.ilu_z, w.ilu_z, st);
+        axpy_f64(w.ilu_z, x, n, st);
+      } else {
+        gemv_update<T>(E.Q().template as<const T>(), w.y, k, nullptr, x, n,
+                       st);
+      }
       R.t[5] += ms_since(tc);
       R.iters += k;
       beta = true_residual();
@@ -771,8 +814,16 @@ void validate_opts(const sgm_opts* o) {
               "restart must be in [1, 4096]");
   SGM_REQUIRE(o->max_restarts >= 0, "max_restarts must be >= 0");
   SGM_REQUIRE(o->tol > 0.0 && std::isfinite(o->tol), "tol must be > 0");
-  SGM_REQUIRE(o->precond == SGM_PRECOND_NONE || o->precond == SGM_PRECOND_JACOBI,
+  SGM_REQUIRE(o->precond == SGM_PRECOND_NONE ||
+                  o->precond == SGM_PRECOND_JACOBI ||
+                  o->precond == SGM_PRECOND_ILU0,
               "unknown preconditioner");
+  if (o->precond == SGM_PRECOND_ILU0) {
+    SGM_REQUIRE(o->precision == SGM_FP64,
+                "the ILU(0) preconditioner runs in float64 only");
+    SGM_REQUIRE(o->transpose == 0,
+                "the ILU(0) preconditioner is not available for A^T solves");
+  }
   SGM_REQUIRE(o->basis == SGM_BASIS_SCALED_NEWTON ||
                   o->basis == SGM_BASIS_NEWTON ||
                   o->basis == SGM_BASIS_MONOMIAL,
@@ -809,7 +860,8 @@ size_t solve_ws_bytes(const Matrix& M, const sgm_opts& o) {
   Work w;
   const int64_t snnz = std::max(M.fwd.nnz_padded, M.trn.nnz_padded);
   layout(a, w, M.n, snnz, o.restart, o.s_max, nshift_max(o),
-         o.precision == SGM_FP32_IR, o.precond == SGM_PRECOND_JACOBI);
+         o.precision == SGM_FP32_IR, o.precond == SGM_PRECOND_JACOBI,
+         o.precond == SGM_PRECOND_ILU0);
   return a.off + 256;
 }
 
@@ -1006,6 +1058,44 @@ sgm_status sgm_matrix_destroy(sgm_matrix A) {
   SGM_API_END
 }
 
+sgm_status sgm_matrix_ilu0(sgm_matrix A, void* stream, int32_t* levels) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(A != nullptr, "matrix is NULL");
+  Matrix& M = *handle(A)->M;
+  ilu_build(M, as_stream(stream));
+  if (levels) {
+    levels[0] = M.ilu->L.nlev;
+    levels[1] = M.ilu->U.nlev;
+  }
+  return SGM_OK;
+  SGM_API_END
+}
+
+sgm_status sgm_ilu0_apply(sgm_matrix A, const double* r, double* z,
+                          void* stream) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(A != nullptr && r != nullptr && z != nullptr, "NULL argument");
+  const Matrix& M = *handle(A)->M;
+  SGM_REQUIRE(M.ilu != nullptr && M.ilu->ok,
+              "no valid ILU(0) factors: call sgm_matrix_ilu0 first");
+  ilu_apply(*M.ilu, M.n, colmajor_view<const double>(r, M.n), r, z,
+            as_stream(stream));
+  return SGM_OK;
+  SGM_API_END
+}
+
+sgm_status sgm_ilu0_factors(sgm_matrix A, double* lu, void* stream) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(A != nullptr && lu != nullptr, "NULL argument");
+  const Matrix& M = *handle(A)->M;
+  SGM_REQUIRE(M.ilu != nullptr && M.ilu->ok,
+              "no valid ILU(0) factors: call sgm_matrix_ilu0 first");
+  SGM_HIP(hipMemcpyAsync(lu, M.ilu->fac, sizeof(double) * (size_t)M.nnz,
+                         hipMemcpyDeviceToDevice, as_stream(stream)));
+  return SGM_OK;
+  SGM_API_END
+}
+
 sgm_status sgm_matrix_info(sgm_matrix A, int64_t* n, int64_t* nnz,
                            int64_t* sell_nnz, int32_t* index_bytes) {
   SGM_API_BEGIN
@@ -1096,7 +1186,8 @@ sgm_status sgm_solve(sgm_matrix A, const double* b, const double* x0,
   Work w;
   const int64_t snnz = std::max(h->M->fwd.nnz_padded, h->M->trn.nnz_padded);
   layout(a, w, h->M->n, snnz, o->restart, o->s_max, nshift_max(*o),
-         o->precision == SGM_FP32_IR, o->precond == SGM_PRECOND_JACOBI);
+         o->precision == SGM_FP32_IR, o->precond == SGM_PRECOND_JACOBI,
+         o->precond == SGM_PRECOND_ILU0);
   Result R;
   sgm_status st = SGM_OK;
   std::string err;

@@ -92,15 +92,18 @@ __device__ __forceinline__ T mpk_row(T sum, T xo, T xp, bool has_prev,
 
 // x, xprev and y are columns of a block of vectors with layout XV (row r of
 // a column at column base + XV.row_off(r)); the plain and residual
-// epilogues use contiguous vectors (column-major view).
+// epilogues use contiguous vectors (column-major view).  The matrix
+// multiplies xm with layout XM: x itself, or with a right preconditioner
+// z = M^{-1} x while the recurrence's shift terms still use x.
 template <typename T, int EPI, typename IDX>
 __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
     const int64_t* __restrict__ ptr, const int32_t* __restrict__ width,
     const IDX* __restrict__ col, const int32_t* __restrict__ kbase,
     const T* __restrict__ val, QView<T> XV, const T* __restrict__ x,
-    const T* __restrict__ xprev, T* __restrict__ y,
-    const double* __restrict__ b, double* __restrict__ part, int64_t n,
-    int64_t nslices, const double* __restrict__ rec, int j, int xcd_contig) {
+    QView<T> XM, const T* __restrict__ xm, const T* __restrict__ xprev,
+    T* __restrict__ y, const double* __restrict__ b,
+    double* __restrict__ part, int64_t n, int64_t nslices,
+    const double* __restrict__ rec, int j, int xcd_contig) {
   // Workgroup b runs on XCD b % 8.  With xcd_contig each XCD takes one
   // contiguous range of slices instead of every eighth group of four, so
   // the x lines that neighbouring slices share are fetched into one L2.
@@ -130,7 +133,7 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
   } else if constexpr (EPI == EPI_RESID) {
     if (r < n) bb = b[r];
   }
-  const T sum = sell_row_dot<T, IDX>(ptr, width, col, kbase, val, XV, x,
+  const T sum = sell_row_dot<T, IDX>(ptr, width, col, kbase, val, XM, xm,
                                      nslices, s, lane);
   if constexpr (EPI == EPI_PLAIN) {
     if (r < n) y[r] = sum;
@@ -286,6 +289,11 @@ __global__ void k_copy(const double* a, double* b, int64_t n) {
   if (i < n) b[i] = a[i];
 }
 
+__global__ void k_axpy(const double* z, double* x, int64_t n) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) x[i] += z[i];
+}
+
 inline unsigned g1(int64_t n) {
   return (unsigned)ceil_div(n > 0 ? n : 1, 256);
 }
@@ -298,7 +306,8 @@ void spmv_plain(const Sell& S, const T* val, const T* x, T* y,
 #define SGM_SPMV(IDX, colp)                                                   \
   hipLaunchKernelGGL((k_spmv<T, EPI_PLAIN, IDX>), dim3(spmv_grid(S)),         \
                      dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, S.kbase,  \
-                     val, colmajor_view<T>(nullptr, 0), x, (const T*)nullptr, \
+                     val, colmajor_view<T>(nullptr, 0), x,                    \
+                     colmajor_view<T>(nullptr, 0), x, (const T*)nullptr,      \
                      y, (const double*)nullptr, (double*)nullptr, S.n,        \
                      S.nslices, (const double*)nullptr, 0,                    \
                      xcd_contig(S, (int)sizeof(T)))
@@ -314,9 +323,9 @@ void spmv_mpk(const Sell& S, const T* val, QView<T> Q, int jx, int jprev,
 #define SGM_SPMV(IDX, colp)                                                   \
   hipLaunchKernelGGL((k_spmv<T, EPI_MPK, IDX>), dim3(spmv_grid(S)),           \
                      dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, S.kbase,  \
-                     val, Q, (const T*)Q.col(jx), xp, Q.col(jy),              \
-                     (const double*)nullptr, (double*)nullptr, S.n,           \
-                     S.nslices, rec, j, xcd_contig(S, (int)sizeof(T)))
+                     val, Q, (const T*)Q.col(jx), Q, (const T*)Q.col(jx), xp, \
+                     Q.col(jy), (const double*)nullptr, (double*)nullptr,     \
+                     S.n, S.nslices, rec, j, xcd_contig(S, (int)sizeof(T)))
   if (S.rcol) SGM_SPMV(int16_t, S.rcol); else SGM_SPMV(int32_t, S.col);
 #undef SGM_SPMV
   SGM_CHECK_LAUNCH();
@@ -403,6 +412,23 @@ void spmv_mpk_steps(const Sell& S, const T* val, QView<T> Q,
   }
 }
 
+void spmv_mpk_prec(const Sell& S, const double* val, QView<double> Q,
+                   const double* z, int jx, int jprev, int jy,
+                   const double* rec, int j, hipStream_t st) {
+  const double* xp =
+      jprev >= 0 ? (const double*)Q.col(jprev) : (const double*)nullptr;
+#define SGM_SPMV(IDX, colp)                                                   \
+  hipLaunchKernelGGL((k_spmv<double, EPI_MPK, IDX>), dim3(spmv_grid(S)),      \
+                     dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, S.kbase,  \
+                     val, Q, (const double*)Q.col(jx),                        \
+                     colmajor_view<double>(nullptr, 0), z, xp, Q.col(jy),     \
+                     (const double*)nullptr, (double*)nullptr, S.n,           \
+                     S.nslices, rec, j, xcd_contig(S, (int)sizeof(double)))
+  if (S.rcol) SGM_SPMV(int16_t, S.rcol); else SGM_SPMV(int32_t, S.col);
+#undef SGM_SPMV
+  SGM_CHECK_LAUNCH();
+}
+
 template void spmv_mpk_steps<double>(const Sell&, const double*,
                                      QView<double>, const MpkStep*, int,
                                      const double*, const MpkPlan&,
@@ -419,6 +445,7 @@ int64_t spmv_resid(const Sell& S, const double* val, const double* x,
   hipLaunchKernelGGL((k_spmv<double, EPI_RESID, IDX>), dim3(spmv_grid(S)),    \
                      dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, S.kbase,  \
                      val, colmajor_view<double>(nullptr, 0), x,               \
+                     colmajor_view<double>(nullptr, 0), x,                    \
                      (const double*)nullptr, r, b, part, S.n, S.nslices,      \
                      (const double*)nullptr, 0, 0)
   if (S.rcol) SGM_SPMV(int16_t, S.rcol); else SGM_SPMV(int32_t, S.col);
@@ -491,6 +518,11 @@ void grad_vals(const Matrix& M, const double* lam, const double* x,
 
 void cast_f64_f32(const double* a, float* b, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(k_cast, dim3(g1(n)), dim3(256), 0, st, a, b, n);
+  SGM_CHECK_LAUNCH();
+}
+
+void axpy_f64(const double* z, double* x, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy, dim3(g1(n)), dim3(256), 0, st, z, x, n);
   SGM_CHECK_LAUNCH();
 }
 
