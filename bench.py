@@ -43,7 +43,14 @@ line; no CPU baseline, whose bounded sample would not fit in minutes):
                 with C cycles;
   banded_1m     random banded nonsymmetric n = 1M, 27 nonzeros per row:
                 the differentiable solve to 1e-12, forward and backward
-                (adjoint solve + gradient w.r.t. the CSR values).
+                (adjoint solve + gradient w.r.t. the CSR values);
+  laplace2d_400_ilu0
+                2D Laplace 400^2 (n = 160,000) with right ILU(0), the
+                setting of the paper's test with an ILU preconditioner:
+                float64 to 1e-10 with default options and with the paper's
+                settings for that test (s0 = 256), and without the
+                preconditioner; the factorisation and one M^{-1}
+                application timed apart.
 """
 from __future__ import annotations
 
@@ -245,6 +252,90 @@ def spmv_roofline(A, G, rs, vb, label):
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches": int(n_spmv)}
 
 
+def study_ilu(args, np, torch, sgm, W):
+    """2D Laplace 400^2 (the matrix of the paper's Test 2) with right ILU(0),
+    the setting of its Sec. 4.3 test with an ILU preconditioner, to 1e-10:
+    - fp64_ilu0: default options (s_max 256, the library's largest step,
+      restart 400, estimator on, pre-phase columns reused);
+    - fp64_ilu0_separate_prephase: the paper's settings for that test (a
+      separate Ritz pre-phase, no estimator, Omega = 1e7), s0 = 256;
+    - fp64_none: the same system without a preconditioner.
+    The factorisation (sgm_matrix_ilu0) is matrix analysis and is timed
+    apart; one M^{-1} application is timed on its own as well."""
+    A = W.laplace_2d(400)
+    b_host = W.rhs(A.n, 1)
+    G = sgm.Matrix.from_csr(A)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    levels = G.ilu0()
+    torch.cuda.synchronize()
+    t_fac = (time.perf_counter() - t0) * 1e3
+    b = torch.tensor(b_host, device="cuda")
+    x = torch.empty_like(b)
+    ws = sgm.Workspace()
+    base = dict(s_max=256, restart=400, tol=1e-10, max_restarts=100)
+    modes = [("fp64_ilu0", dict(base, precond="ilu0")),
+             ("fp64_ilu0_separate_prephase",
+              dict(base, precond="ilu0", ritz_reuse=False,
+                   use_estimator=False, omega=1e7)),
+             ("fp64_none", dict(base))]
+    for mname, o in modes:
+        sgm.solve(G, b, out=x, workspace=ws, **dict(o, max_restarts=0))
+        torch.cuda.synchronize()
+    per, infos = {}, {}
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        for mname, o in modes:
+            t0 = time.perf_counter()
+            r = sgm.solve(G, b, out=x, workspace=ws, **o)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            per.setdefault(mname, []).append(ms)
+            infos.setdefault(mname, []).append(r)
+            log(f"[bench] step {k} {mname}: {ms:.1f} ms iters "
+                f"{r.info['iters']} rel {r.info['rel_res_true']:.2e}")
+    total_ms = (time.perf_counter() - t_start) * 1e3
+    # one M^{-1} application, timed alone (HIP events on torch's stream)
+    z = torch.empty_like(b)
+    for _ in range(3):
+        G.ilu0_apply(b, out=z)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(
+        enable_timing=True)
+    reps = 50
+    e0.record()
+    for _ in range(reps):
+        G.ilu0_apply(b, out=z)
+    e1.record()
+    torch.cuda.synchronize()
+    apply_us = e0.elapsed_time(e1) * 1e3 / reps
+    out = {"metric": METRIC, "unit": "ms", "n_gpus": 1,
+           "steps": args.steps, "warmup": 1,
+           "ms_per_step": round(total_ms / max(1, args.steps), 3),
+           "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic",
+           "config": {"workload": "laplace2d_400_ilu0",
+                      "matrix": "2D Laplace 5-point (4, -1) 400^2, Dirichlet",
+                      "precond": "ILU(0), right", "n": A.n, "nnz": A.nnz,
+                      "basis": "scaled_newton", "s_max": 256,
+                      "restart": 400, "tol": 1e-10, "rhs": "N(0,1) seed 1",
+                      "x0": "zero"}}
+    for mname, _ in modes:
+        out[mname] = solve_summary(sgm, infos[mname], per[mname], 1e-10)
+    out["value"] = out["fp64_ilu0"]["ms"]
+    out["dtype"] = "f64"
+    nl = int(levels[0]) + int(levels[1])
+    out["ilu0"] = {"factorisation_ms": round(t_fac, 3),
+                   "levels": [int(levels[0]), int(levels[1])],
+                   "apply_us": round(apply_us, 2),
+                   "apply_ns_per_level": round(apply_us * 1e3 / nl, 1),
+                   "bound": "latency: one workgroup walks the levels, "
+                            "with LDS reads, its arithmetic and one barrier "
+                            "per level"}
+    out["roofline"] = None
+    out["cpu_baseline"] = None
+    return out
+
+
 def study(args, np, torch, sgm, W):
     """One JSON line for a workload other than the default (see the module
     docstring): every mode is warmed up once with its restarts capped at
@@ -255,6 +346,8 @@ def study(args, np, torch, sgm, W):
         return study_adjoint(args, np, torch, sgm, W)
     if name == "aniso2d_4096" and args.to_tol:
         return study_to_tol(args, np, torch, sgm, W)
+    if name == "laplace2d_400_ilu0":
+        return study_ilu(args, np, torch, sgm, W)
     if name == "varcd3d_192":
         A = W.var_conv_diff_3d(192, 3)
         b_host = W.rhs(A.n, 3)
@@ -536,7 +629,7 @@ def main():
     ap.add_argument("--nx", type=int, default=128)
     ap.add_argument("--workload", default="poisson3d_128",
                     choices=["poisson3d_128", "varcd3d_192", "aniso2d_4096",
-                             "banded_1m"])
+                             "banded_1m", "laplace2d_400_ilu0"])
     ap.add_argument("--mode", choices=["both", "fp64", "fp32_ir", "all"],
                     default="all")
     ap.add_argument("--grid", type=int, default=0,

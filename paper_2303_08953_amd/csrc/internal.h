@@ -134,20 +134,29 @@ struct Sell {
 struct IluLevels {
   int32_t nlev = 0;           // levels (host copy)
   int32_t width = 0;          // largest row of the triangle (host copy)
+  int32_t wpad = 0;           // ELL columns stored (>= width)
+  int32_t max_level = 0;      // rows of the largest level (host copy)
   int32_t* rows = nullptr;    // [n] rows in level order
   int32_t* lptr = nullptr;    // [nlev + 1] first position of each level
   int32_t* cnt = nullptr;     // [n]
-  int32_t* ecol = nullptr;    // [width * n]
-  int32_t* esrc = nullptr;    // [width * n] CSR index of the entry, -1 pad
-  double* eval = nullptr;     // [width * n] factor values
+  int32_t* ecol = nullptr;    // [wpad * n]
+  int32_t* epos = nullptr;    // [wpad * n] the column's level-order position
+  int32_t* esrc = nullptr;    // [wpad * n] CSR index of the entry, -1 pad
+  double* eval = nullptr;     // [wpad * n] factor values, 0 in the padding
 };
 struct Ilu {
   int32_t* dpos = nullptr;     // [n] CSR index of each diagonal entry
   double* fac = nullptr;       // [nnz] L (strict lower) and U, CSR order
   double* dinv = nullptr;      // [n] 1 / u_rr in backward-level order
-  int32_t* nlev_dev = nullptr; // [2] levels of the forward, backward side
+  int32_t* nlev_dev = nullptr; // [4] levels of the forward, backward side;
+                               // far flags of each (solve: LDS-only barrier
+                               // when 0)
   int32_t* flags = nullptr;    // [4] analysis / pivot flags
   IluLevels L, U;
+  int32_t max_level = 0;       // rows of the largest level, both sides
+  int32_t* l2u = nullptr;      // [n] backward position of each forward one
+  double* tl = nullptr;        // [n] solve scratch (forward level order)
+  double* tu = nullptr;        // [n] solve scratch (backward level order)
   bool ok = false;             // factors valid for the current values
 };
 

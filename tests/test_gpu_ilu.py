@@ -4,9 +4,11 @@ oracle's ILU0 and its preconditioned solves.
 
 - factors: the GPU factorisation (levels of the forward substitution, IKJ
   elimination on the pattern) against the oracle's L and U at every stored
-  entry, on 2D and 3D stencils and a random nonsymmetric pattern whose rows
-  hold more than eight entries on one side of the diagonal; the level
-  counts against the closed forms 2N - 1 (N x N grid) and 3N - 2 (N^3);
+  entry, on 2D and 3D stencils, a random nonsymmetric pattern whose rows
+  hold more than eight entries on one side of the diagonal, and a matrix
+  whose second level depends on rows more than 16384 positions back (the
+  solve's global-memory path); the level counts against the closed forms
+  2N - 1 (N x N grid) and 3N - 2 (N^3);
 - M^{-1} r against the oracle's two triangular solves, also in place;
 - invalid input: no stored diagonal, unsorted columns, a zero pivot;
 - new values through sgm_matrix_update_values refactor;
@@ -55,10 +57,22 @@ def _random_pattern(n=3000, seed=11, per_row=24):
     return (A + sp.diags(d)).tocsr()
 
 
+def _two_levels(n=40000):
+    """4 I with -1 couplings n/2 apart: two levels of n/2 rows each, so the
+    second level depends on positions more than 16384 back (read from
+    global memory, with the full barrier between levels)."""
+    h = n // 2
+    return sp.diags([-np.ones(h), 4.0 * np.ones(n), -np.ones(h)],
+                    [-h, 0, h]).tocsr()
+
+
 CASES = [
     ("laplace2d_40", lambda: csr(W.laplace_2d(40)), (79, 79)),
+    ("two_levels_40000", _two_levels, (2, 2)),
     ("convdiff2d_33", lambda: csr(W.conv_diff_2d(33, 10.0)), (65, 65)),
     ("poisson3d_11", lambda: csr(W.poisson_3d(11)), (31, 31)),
+    # levels of up to about 1200 rows: the 1024-thread solve
+    ("poisson3d_40", lambda: csr(W.poisson_3d(40)), (118, 118)),
     ("random_3000", lambda: _random_pattern(), None),
 ]
 
