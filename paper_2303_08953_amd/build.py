@@ -3,7 +3,10 @@
 Run as `python -m paper_2303_08953_amd.build` or through
 `__graft_entry__.build()`.  Every source under csrc/ is compiled with hipcc
 for --offload-arch=gfx950 and linked into one shared library.  Packed FP32
-VALU forms are disabled for device code.
+VALU forms are disabled for device code.  Each source's gfx950 assembly is
+also emitted (and discarded): printing it checks every instruction's operand
+classes, which the object writer does not, so an instruction the compiler
+formed with an illegal operand fails the build instead of being encoded.
 """
 from __future__ import annotations
 
@@ -52,12 +55,27 @@ def _compile(src: str, verbose: bool, resource_usage: bool) -> str:
     return obj
 
 
+def _check_asm(src: str) -> None:
+    out = os.path.join(BUILD, os.path.splitext(src)[0] + ".s")
+    cmd = [hipcc(), *[f for f in FLAGS if f != "-fPIC"], "--cuda-device-only",
+           "-S", os.path.join(CSRC, src), "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
+                        if "packed-fp32-ops" not in l)
+        raise RuntimeError(f"gfx950 assembly of {src} failed:\n{msg}")
+    os.remove(out)
+
+
 def build(verbose: bool = False, resource_usage: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    jobs = min(len(SOURCES), max(1, (os.cpu_count() or 2)))
+    jobs = min(2 * len(SOURCES), max(1, (os.cpu_count() or 2)))
     with cf.ThreadPoolExecutor(jobs) as ex:
+        checks = [ex.submit(_check_asm, s) for s in SOURCES]
         objs = list(ex.map(lambda s: _compile(s, verbose, resource_usage),
                            SOURCES))
+        for c in checks:
+            c.result()
     tmp = OUT + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs,
            "-o", tmp]
