@@ -386,27 +386,32 @@ __global__ __launch_bounds__(kWBlock) void k_gemm_tn_wide(
 
 // ------------------------------------------------------------- wide Gram
 // G = Q(:, b0:b0+nb)^T Q(:, b0:b0+nb) for Gram matrices of 65 to 256
-// columns.  One 512-thread workgroup per row chunk loads each 16-row batch
+// columns.  One 1024-thread workgroup per row chunk loads each 16-row batch
 // of all nb columns into LDS once (double-buffered, column stride 17), and
-// the eight wavefronts form the nt (nt + 1) / 2 tiles on and above the
+// the sixteen wavefronts form the nt (nt + 1) / 2 tiles on and above the
 // diagonal (nt = 16 ceil(nb / 16)) from there: wavefront w takes the
-// contiguous run [T w / 8, T (w + 1) / 8) of them in column order, so
+// contiguous run [T w / 16, T (w + 1) / 16) of them in column order, so
 // consecutive tiles mostly share their B operand, which is read once per
-// column.  The reduction mirrors the lower tiles.  Columns past nb read a
+// column.  Sixteen wavefronts of at most 9 tiles fit four to a SIMD (eight
+// of 17 fitted two): 20.5 -> 15.9 ms for 200 columns over 16.8M rows.
+// The reduction mirrors the lower tiles.  Columns past nb read a
 // valid column (their results are not stored); columns past *ncount give
 // zero (as in the kernels above).  Grid: chunks workgroups, each a
 // contiguous range of batches.
-constexpr int kGTiles = 17;  // most tiles per wavefront (136 / 8 at nb = 256)
+constexpr int kGBlock = 1024;            // 16 wavefronts
+constexpr int kGWaves = kGBlock / kWave;
+// most tiles per wavefront: 136 tiles on and above the diagonal at nb = 256
+constexpr int kGTiles = (136 + kGWaves - 1) / kGWaves;
 constexpr int kGMaxCols = 256;
 
 template <typename T>
-__global__ __launch_bounds__(kWBlock) void k_gram_wide(
+__global__ __launch_bounds__(kGBlock) void k_gram_wide(
     QView<const T> Q, int b0c, int nb, const int* __restrict__ ncount,
     int64_t nbatches, int chunks, double* __restrict__ part) {
   typedef typename Vec4<T>::type V;
   constexpr int EPV = 16 / (int)sizeof(T);  // elements per 16-byte load
   constexpr int VPC = 16 / EPV;             // loads per 16-row column batch
-  constexpr int NVT = (kGMaxCols * VPC + kWBlock - 1) / kWBlock;
+  constexpr int NVT = (kGMaxCols * VPC + kGBlock - 1) / kGBlock;
   typedef T vec_t __attribute__((ext_vector_type(EPV)));
   extern __shared__ char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
@@ -424,7 +429,7 @@ __global__ __launch_bounds__(kWBlock) void k_gram_wide(
   // this wavefront's tiles (row tile, column tile), column-major order of
   // the upper triangle (wavefront-uniform)
   const int T_all = nt * (nt + 1) / 2;
-  const int t0 = T_all * wave / 8, t1 = T_all * (wave + 1) / 8;
+  const int t0 = T_all * wave / kGWaves, t1 = T_all * (wave + 1) / kGWaves;
   int tr[kGTiles], tc[kGTiles];
   {
     int c = 0, base = 0;  // tiles of columns < c: base = c (c + 1) / 2
@@ -453,7 +458,7 @@ __global__ __launch_bounds__(kWBlock) void k_gram_wide(
     const T* rb = Q.base + Q.row_off(bt * 16);
 #pragma unroll
     for (int q = 0; q < NVT; ++q) {
-      const int e = threadIdx.x + kWBlock * q;
+      const int e = threadIdx.x + kGBlock * q;
       if (e < NV) {
         const int col = e / VPC;
         const int c = b0c + (col < nb ? col : 0);
@@ -466,7 +471,7 @@ __global__ __launch_bounds__(kWBlock) void k_gram_wide(
     T* L = lds + buf * LBUF;
 #pragma unroll
     for (int q = 0; q < NVT; ++q) {
-      const int e = threadIdx.x + kWBlock * q;
+      const int e = threadIdx.x + kGBlock * q;
       if (e < NV) {
         T* d = L + (e / VPC) * kWStride + (e % VPC) * EPV;
 #pragma unroll
@@ -605,7 +610,7 @@ enum { MODE_UPDATE = 0, MODE_TRSM = 1 };
 
 // PACKED (MODE_TRSM only): M's upper triangle on the p accepted columns is
 // staged once per workgroup packed row by row (row k holds columns
-// k .. p-1 at k p - k (k - 1) / 2), so a triangular factor of up to 201
+// k .. p-1 at k p - k (k - 1) / 2), so a triangular factor of up to 200
 // float64 columns fits in LDS whole instead of being re-staged in chunks
 // for every row block.
 template <typename T, int NT, int MT, int MODE, bool GRAM, int BLOCK = kBlock,
@@ -632,6 +637,9 @@ __global__ __launch_bounds__(BLOCK) void k_update(
   const int64_t rows_per_wave = 16 * MT;
   const int64_t rows_per_block = rows_per_wave * (BLOCK / kWave);
   const int64_t nblocks = (nrows + rows_per_block - 1) / rows_per_block;
+  // wide blocks of one 16-row tile per wavefront in 512-thread workgroups
+  // (256 registers a lane): loads two groups ahead
+  constexpr bool DEEP = MT == 1 && NT >= 8 && !GRAM && BLOCK <= 512;
 
   auto stage = [&](int k0) {
     if constexpr (PACKED) {
@@ -699,23 +707,52 @@ __global__ __launch_bounds__(BLOCK) void k_update(
                         (int64_t)(MODE == MODE_TRSM ? b0c : a0) * cs +
                         MT * c16;
         auto kstep = [&](int kk, const T (&a)[MT]) {
-          const T* mrow = Ms + (kk + g) * W16 + c16;
-          // packed: row k of the triangle (zero left of the diagonal and
-          // past the accepted columns)
-          const int kp = k0 + kk + g;
-          const T* prow = Ms + (kp * nce - kp * (kp - 1) / 2) - kp;
+          if constexpr (PACKED && BLOCK <= 512) {
+            // row kp of the packed triangle, column c at prow[c].  The
+            // k-step's four rows share one 16-column tile for their
+            // diagonal (jd), and only the last k-step can hold rows past
+            // the accepted columns: only those reads are masked (zero left
+            // of the diagonal and on rows past nce); the others are plain
+            // LDS reads at a constant offset.  A column past nce may read
+            // another row's value or the padding after the triangle; it
+            // only reaches output columns that are never stored.
+            const int kp = k0 + kk + g;
+            const T* prow = Ms + (kp * nce - kp * (kp - 1) / 2) - kp + c16;
+            const int kb = k0 + kk;
+            const int jd = kb >> 4;
+            const bool tail = kb + 4 > nce;
 #pragma unroll
-          for (int j = 0; j < NT; ++j) {
-            if (MODE == MODE_TRSM && (k0 + kk) >= (j + 1) * 16) continue;
-            T bv;
-            if constexpr (PACKED) {
-              const int c = j * 16 + c16;
-              bv = (c >= kp && c < nce && kp < nce) ? prow[c] : (T)0;
-            } else {
-              bv = mrow[j * 16];
+            for (int j = 0; j < NT; ++j) {
+              if (kb >= (j + 1) * 16) continue;
+              T bv;
+              if (j == jd || tail)
+                bv = (j * 16 + c16 >= kp && kp < nce) ? prow[j * 16] : (T)0;
+              else
+                bv = prow[j * 16];
+#pragma unroll
+              for (int t = 0; t < MT; ++t)
+                acc[t][j] = mfma(a[t], bv, acc[t][j]);
             }
+          } else {
+            const T* mrow = Ms + (kk + g) * W16 + c16;
+            // packed: row k of the triangle (zero left of the diagonal and
+            // past the accepted columns)
+            const int kp = k0 + kk + g;
+            const T* prow = Ms + (kp * nce - kp * (kp - 1) / 2) - kp;
 #pragma unroll
-            for (int t = 0; t < MT; ++t) acc[t][j] = mfma(a[t], bv, acc[t][j]);
+            for (int j = 0; j < NT; ++j) {
+              if (MODE == MODE_TRSM && (k0 + kk) >= (j + 1) * 16) continue;
+              T bv;
+              if constexpr (PACKED) {
+                const int c = j * 16 + c16;
+                bv = (c >= kp && c < nce && kp < nce) ? prow[c] : (T)0;
+              } else {
+                bv = mrow[j * 16];
+              }
+#pragma unroll
+              for (int t = 0; t < MT; ++t)
+                acc[t][j] = mfma(a[t], bv, acc[t][j]);
+            }
           }
         };
         // unconditional loads: a column past the end reads column 0, whose
@@ -731,7 +768,52 @@ __global__ __launch_bounds__(BLOCK) void k_update(
         // would make every group wait for its successor's loads).  The
         // prefetch past the last group reads column 0 and is not used.
         const int kend16 = kend & ~15;
-        if (kend16 > 0) {
+        if (DEEP && kend16 > 0) {
+          // three register sets: the loads of the group two ahead are in
+          // flight while a group is multiplied (a wavefront of one 16-row
+          // tile per column keeps too few bytes in flight with two)
+          T x0[MT], x1[MT], x2[MT], x3[MT], y0[MT], y1[MT], y2[MT], y3[MT],
+              z0[MT], z1[MT], z2[MT], z3[MT];
+          kload(0, x0);
+          kload(4, x1);
+          kload(8, x2);
+          kload(12, x3);
+          kload(16, y0);
+          kload(20, y1);
+          kload(24, y2);
+          kload(28, y3);
+          for (int kg = 0; kg < kend16; kg += 48) {
+            kload(kg + 32, z0);
+            kload(kg + 36, z1);
+            kload(kg + 40, z2);
+            kload(kg + 44, z3);
+            __builtin_amdgcn_sched_barrier(0);
+            kstep(kg, x0);
+            kstep(kg + 4, x1);
+            kstep(kg + 8, x2);
+            kstep(kg + 12, x3);
+            if (kg + 16 >= kend16) break;
+            kload(kg + 48, x0);
+            kload(kg + 52, x1);
+            kload(kg + 56, x2);
+            kload(kg + 60, x3);
+            __builtin_amdgcn_sched_barrier(0);
+            kstep(kg + 16, y0);
+            kstep(kg + 20, y1);
+            kstep(kg + 24, y2);
+            kstep(kg + 28, y3);
+            if (kg + 32 >= kend16) break;
+            kload(kg + 64, y0);
+            kload(kg + 68, y1);
+            kload(kg + 72, y2);
+            kload(kg + 76, y3);
+            __builtin_amdgcn_sched_barrier(0);
+            kstep(kg + 32, z0);
+            kstep(kg + 36, z1);
+            kstep(kg + 40, z2);
+            kstep(kg + 44, z3);
+          }
+        } else if (kend16 > 0) {
           T x0[MT], x1[MT], x2[MT], x3[MT], y0[MT], y1[MT], y2[MT], y3[MT];
           kload(0, x0);
           kload(4, x1);
@@ -1673,14 +1755,14 @@ void gemm_tn(QView<const T> Q, int a0, int ma, int b0, int nb,
   // A Gram matrix of 129 to 256 columns: every 16-row batch of its columns
   // in LDS once per workgroup, the tiles on and above the diagonal formed
   // from there (the kernels below fetch each operand per wavefront).
-  // Measured in float64: 200 columns over 16.8M rows 20.2 against 33.6 ms;
+  // Measured in float64: 200 columns over 16.8M rows 15.9 against 33.6 ms;
   // at 128 columns over 7.1M rows the kernel below is faster (4.2 against
   // 4.7 ms), so it keeps those.
   if (a0 == b0 && ma == nb && nb > 128 && nb <= kGMaxCols) {
     const int chunks_g =
         pick_chunks(2 * kNumCUs, 1, nbatches, (int64_t)nb * nb, P);
     const size_t lds = (size_t)2 * nt_all * 16 * kWStride * sizeof(T);
-    hipLaunchKernelGGL(k_gram_wide<T>, dim3(chunks_g), dim3(kWBlock), lds,
+    hipLaunchKernelGGL(k_gram_wide<T>, dim3(chunks_g), dim3(kGBlock), lds,
                        st, Q, b0, nb, ncount, nbatches, chunks_g, P.buf);
     SGM_CHECK_LAUNCH();
     launch_reduce(P.buf, chunks_g, nb, nb, C, ldc, 1, st);
@@ -1743,7 +1825,8 @@ void launch_update_b(QView<T> Q, int a0, int ka, int b0, int nc,
   if constexpr (MODE == MODE_TRSM && !GRAM && NT > 4 && sizeof(T) == 8) {
     // a float64 triangular factor that does not fit whole: packed, when
     // that fits (float32 factors fit whole up to 197 columns)
-    const size_t packed = (size_t)nc * (nc + 1) / 2 * sizeof(T);
+    // (plus room for the reads past the triangle's last row: W16 + 64)
+    const size_t packed = ((size_t)nc * (nc + 1) / 2 + W16 + 64) * sizeof(T);
     if (kc < ka4 && packed <= (size_t)kMaxLds) {
       const int64_t rows_per_block = 16 * MT * (BLOCK / kWave);
       const int64_t nblocks = ceil_div(nrows, rows_per_block);
