@@ -384,6 +384,156 @@ __global__ __launch_bounds__(kWBlock) void k_gemm_tn_wide(
     }
 }
 
+// ------------------------------------------------------------- tall A^T B
+// C = Q(:, a0:a0+ma)^T Q(:, b0:b0+nb) for 145 to 208 rows (ma) and more than
+// 96 columns, not a Gram matrix: the 144 x 128 blocks above would compute
+// 288 x 256 for 201 x 200 (55% of it used) and read each column about 2.7
+// times.  Here a workgroup covers all ma rows (13 tiles) and at most 112
+// columns (7 tiles): each 16-row batch of those 208 + 112 columns is
+// loaded into LDS once, and sixteen wavefronts take contiguous runs of at
+// most 6 of the block's 91 tiles in column order (the B operand is read
+// once per column of a run), as in the wide Gram.  Columns past ma / nbe
+// read a valid column; their results are not stored (rows past ma) or
+// stored as zero (columns past nbe).  Grid: nblk * chunks workgroups
+// (chunks a multiple of 8), decoded XCD-aware like the kernel above.
+constexpr int kRM = 13, kRN = 7;           // tiles per output block
+constexpr int kRCols = 16 * (kRM + kRN);   // 320 columns per batch
+constexpr int kRBlock = 1024;
+constexpr int kRWaves = kRBlock / kWave;
+constexpr int kRTiles = (kRM * kRN + kRWaves - 1) / kRWaves;
+
+template <typename T>
+__global__ __launch_bounds__(kRBlock) void k_gemm_tn_tall(
+    QView<const T> Q, int a0, int ma, int b0c, int nb,
+    const int* __restrict__ ncount, int64_t nbatches, int nblk, int chunks,
+    double* __restrict__ part) {
+  typedef typename Vec4<T>::type V;
+  constexpr int EPV = 16 / (int)sizeof(T);  // elements per 16-byte load
+  constexpr int VPC = 16 / EPV;             // loads per 16-row column batch
+  constexpr int NV = kRCols * VPC;          // loads per batch
+  constexpr int NVT = (NV + kRBlock - 1) / kRBlock;
+  constexpr int LBUF = kRCols * kWStride;   // elements per LDS buffer
+  typedef T vec_t __attribute__((ext_vector_type(EPV)));
+  extern __shared__ char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int lane = threadIdx.x % kWave;
+  const int g = lane / 16, c16 = lane % 16;
+  const int id = blockIdx.x;
+  const int xcd = id % 8, slot = id / 8;
+  const int blk = slot % nblk;
+  const int chunk = (slot / nblk) * 8 + xcd;
+  const int n0 = blk * 16 * kRN;
+  const int nbe = ncount ? min(nb, *ncount) : nb;
+  const int nta = (ma + 15) / 16;                       // <= kRM
+  const int ntb = min(kRN, (nb - n0 + 15) / 16);        // this block's
+  const int64_t bt0 = nbatches * chunk / chunks;
+  const int64_t bt1 = nbatches * (chunk + 1) / chunks;
+  // this wavefront's tiles (row tile, column tile), column-major order
+  const int T_all = nta * ntb;
+  const int t0 = T_all * wave / kRWaves, t1 = T_all * (wave + 1) / kRWaves;
+  const int cnt = t1 - t0;
+  int tr[kRTiles], tc[kRTiles];
+#pragma unroll
+  for (int u = 0; u < kRTiles; ++u) {
+    tr[u] = (t0 + u) % nta;
+    tc[u] = (t0 + u) / nta;
+  }
+  // column offset in Q of batch column `col` (A columns, then B columns)
+  auto qcol = [&](int col) -> int64_t {
+    int c;
+    if (col < 16 * kRM) {
+      c = a0 + (col < ma ? col : 0);
+    } else {
+      const int cb = n0 + col - 16 * kRM;
+      c = b0c + (cb < nbe ? cb : 0);
+    }
+    return (int64_t)c * Q.cstride;
+  };
+  // three register stages in a ring: the loads of batch b + 1 go out two
+  // batches before b + 1 is stored to LDS
+  vec_t sA[NVT], sB[NVT], sC[NVT];
+  auto gload = [&](int64_t bt, vec_t (&stg)[NVT]) {
+    const T* rb = Q.base + Q.row_off(bt * 16);
+#pragma unroll
+    for (int q = 0; q < NVT; ++q) {
+      const int e = threadIdx.x + kRBlock * q;
+      if (e < NV)
+        stg[q] = *reinterpret_cast<const vec_t*>(rb + qcol(e / VPC) +
+                                                 (e % VPC) * EPV);
+    }
+  };
+  auto lstore = [&](int buf, const vec_t (&stg)[NVT]) {
+    T* L = lds + buf * LBUF;
+#pragma unroll
+    for (int q = 0; q < NVT; ++q) {
+      const int e = threadIdx.x + kRBlock * q;
+      if (e < NV) {
+        T* d = L + (e / VPC) * kWStride + (e % VPC) * EPV;
+#pragma unroll
+        for (int u = 0; u < EPV; ++u) d[u] = stg[q][u];
+      }
+    }
+  };
+  V acc[kRTiles];
+#pragma unroll
+  for (int u = 0; u < kRTiles; ++u) acc[u] = vzero<V>();
+  auto compute = [&](int buf) {
+    const T* L = lds + buf * LBUF + c16 * kWStride + g;
+    const T* Lb = L + 16 * kRM * kWStride;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int cur = -1;
+      T bv = 0;
+#pragma unroll
+      for (int u = 0; u < kRTiles; ++u) {
+        if (u < cnt) {
+          if (tc[u] != cur) {
+            cur = tc[u];
+            bv = Lb[cur * 16 * kWStride + 4 * q];
+          }
+          acc[u] = mfma(L[tr[u] * 16 * kWStride + 4 * q], bv, acc[u]);
+        }
+      }
+    }
+  };
+  int buf = 0;
+  auto step = [&](int64_t b, const vec_t (&nxt)[NVT], vec_t (&fre)[NVT]) {
+    if (b >= bt1) return;
+    compute(buf);
+    if (b + 1 < bt1) lstore(buf ^ 1, nxt);
+    if (b + 3 < bt1) gload(b + 3, fre);
+    __syncthreads();
+    buf ^= 1;
+  };
+  if (bt0 < bt1) {
+    gload(bt0, sA);
+    lstore(0, sA);
+  }
+  if (bt0 + 1 < bt1) gload(bt0 + 1, sB);
+  if (bt0 + 2 < bt1) gload(bt0 + 2, sC);
+  __syncthreads();
+  for (int64_t bt = bt0; bt < bt1; bt += 3) {
+    step(bt, sB, sA);
+    step(bt + 1, sC, sB);
+    step(bt + 2, sA, sC);
+  }
+  double* out = part + (int64_t)chunk * ma * nb;
+#pragma unroll
+  for (int u = 0; u < kRTiles; ++u) {
+    if (u < cnt) {
+      const int col = n0 + tc[u] * 16 + c16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = tr[u] * 16 + drow<T>(g, r);
+        if (row < ma && col < nb)
+          out[(int64_t)col * ma + row] =
+              col < nbe ? (double)acc[u][r] : 0.0;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------- wide Gram
 // G = Q(:, b0:b0+nb)^T Q(:, b0:b0+nb) for Gram matrices of 65 to 256
 // columns.  One 1024-thread workgroup per row chunk loads each 16-row batch
@@ -1733,6 +1883,21 @@ void gemm_tn(QView<const T> Q, int a0, int ma, int b0, int nb,
   groups = groups < 256 ? 256 : (groups > 1024 ? 1024 : groups);
   const int chunks =
       pick_chunks((int)groups, ngroups, nbatches, (int64_t)ma * nb, P);
+  if (mt_all > kWM && mt_all <= kRM && nt_all > 6 &&
+      !(a0 == b0 && ma == nb)) {
+    // 145 to 208 rows, more than 96 columns: all rows per workgroup
+    // (measured at 201 x 200 over 16.8M rows, float64: see the kernel)
+    const int nblk = (nt_all + kRN - 1) / kRN;
+    const int chunks_t =
+        pick_chunks(2 * kNumCUs, nblk, nbatches, (int64_t)ma * nb, P);
+    const size_t lds = (size_t)2 * kRCols * kWStride * sizeof(T);
+    hipLaunchKernelGGL(k_gemm_tn_tall<T>, dim3(chunks_t * nblk),
+                       dim3(kRBlock), lds, st, Q, a0, ma, b0, nb, ncount,
+                       nbatches, nblk, chunks_t, P.buf);
+    SGM_CHECK_LAUNCH();
+    launch_reduce(P.buf, chunks_t, ma, nb, C, ldc, 0, st);
+    return;
+  }
   if (mt_all > 4 && nt_all > 6 && !(a0 == b0 && ma == nb)) {
     // more than 64 rows and 96 columns, not a Gram matrix: the LDS-shared
     // kernel, whose 144 x 128 blocks are then mostly full (measured in the

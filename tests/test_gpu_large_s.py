@@ -76,12 +76,15 @@ def _check_block(lib, Qi, V, omega=None, spread=None):
 
 
 @pytest.mark.parametrize("i,s", [(1, 64), (40, 100), (129, 128), (7, 200),
-                                 (64, 256), (150, 100), (200, 200)])
+                                 (64, 256), (150, 100), (200, 200),
+                                 (208, 113)])
 def test_block_orth_wide_full_rank(lib, i, s):
     """A well-conditioned block: every column is accepted (p = s), so every
     column tile of the update, triangular solve and Gram products is live.
     (129, 128) runs the LDS-shared projection kernel on one 144 x 128
-    output block; (150, 100) and (200, 200) on two and four blocks."""
+    output block; (150, 100), (200, 200) and (208, 113) the kernel that
+    holds all 145 to 208 rows per workgroup, on one, two and two (7 + 1
+    column tiles) blocks."""
     rng = np.random.default_rng(100 + s)
     n = 21 ** 3   # 9261, ragged
     Qi, _ = np.linalg.qr(rng.standard_normal((n, i)))
