@@ -210,14 +210,19 @@ typedef struct {
   double rel_res_true;    /* final ||b - A x|| / ||b - A x0|| (float64)      */
   double rel_res_est;     /* last Givens estimate                            */
   double t_phase_ms[8];   /* 0 setup (host wall), 1 pre-phase + shifts (host
-                             wall), 2 MPK, 3 block orthogonalisation, 4
-                             Hessenberg + Givens (GPU time between HIP events
-                             on the solve's stream), 5 cycle end: update +
-                             true residual (host wall), 6 refinement loop
-                             (host wall), 7 total (host wall)                */
+                             wall), 2 MPK, 3 block orthogonalisation with
+                             the Hessenberg recovery, Givens rotations and
+                             convergence test (GPU time between HIP events on
+                             the solve's stream: from a block's last matrix
+                             powers step to the next block's first), 4 unused
+                             (0), 5 cycle end: update + true residual (host
+                             wall), 6 refinement loop (host wall), 7 total
+                             (host wall)                                     */
   int64_t n_spmv;         /* SpMV launches of the matrix powers kernel       */
-  double t_spmv_ms;       /* their GPU time: one HIP event pair around the
-                             back-to-back launches of each block's MPK       */
+  double t_spmv_ms;       /* their GPU time: one HIP event pair around each
+                             block's matrix powers steps (queued back to
+                             back; the first few may be queued behind the
+                             previous block, see sgm_solve)                  */
   int32_t mpk_depth;      /* depth the matrix powers kernel ran at           */
   int64_t mpk_slab_rows;  /* rows per slab of the fused kernel (0: depth 1) */
 } sgm_info;
@@ -233,7 +238,14 @@ sgm_status sgm_workspace_size(sgm_matrix A, const sgm_opts* o,
  * estimate after every iteration; s_hist (host, capacity s_cap, may be NULL)
  * the accepted block size of every block (0 marks a breakdown block).
  * info (host, may be NULL).  Returns SGM_OK when the true relative residual
- * reaches tol, SGM_NOT_CONVERGED when the caps are hit first. */
+ * reaches tol, SGM_NOT_CONVERGED when the caps are hit first.
+ * Scheduling: after each block's tail the first few matrix powers steps of
+ * the next block are queued at once, on the assumption that every column
+ * of the block is accepted (the next block then has the same size); each
+ * of them reads a control word the tail wrote and does nothing when the
+ * assumption failed or the cycle ended, and the host queues the block
+ * again in full.  The host waits for a tail by polling a word the tail
+ * writes into mapped host memory.  Results do not depend on this. */
 sgm_status sgm_solve(sgm_matrix A, const double* b, const double* x0,
                      double* x, const sgm_opts* o, void* ws, size_t ws_bytes,
                      void* stream, double* res_hist, int32_t res_cap,

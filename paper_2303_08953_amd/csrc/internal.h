@@ -208,9 +208,12 @@ void spmv_plain(const Sell& S, const T* val, const T* x, T* y,
                 hipStream_t st);
 // y = ((A x) - theta x - delta xprev) / gamma with (theta, gamma, delta) =
 // rec[3 j .. 3 j + 2] read on the device.
+// With gate given, the launch does nothing unless *gate == expect (read on
+// the device when the kernel starts).
 template <typename T>
 void spmv_mpk(const Sell& S, const T* val, QView<T> Q, int jx, int jprev,
-              int jy, const double* rec, int j, hipStream_t st);
+              int jy, const double* rec, int j, hipStream_t st,
+              const int* gate = nullptr, int expect = 0);
 // The same step with a right preconditioner: y = ((A z) - theta x -
 // delta xprev) / gamma, z = M^{-1} x given as a plain vector (float64).
 void spmv_mpk_prec(const Sell& S, const double* val, QView<double> Q,
@@ -379,6 +382,12 @@ enum Ctrl {
 // a cycle (convergence, breakdown or a non-finite estimate) when the host
 // has queued further steps without waiting; later tails then do nothing.
 constexpr int C_STOP = C_NCTRL;
+// Device-only word written by every block tail: the accepted size p2 when
+// the cycle goes on, -1 when it ends.  Matrix powers steps of the next
+// block queued before the host has seen the tail's result carry the size
+// they assume and do nothing unless it matches.
+constexpr int C_GO = C_NCTRL + 1;
+constexpr int kCtrlWords = C_NCTRL + 2;
 
 void pchol_ice(const double* G, int ldg, int smax, const int* s_dev,
                double omega, double* R, double* Rinv, int ldr, int* p_out,
@@ -395,6 +404,10 @@ void combine_r(const double* W, int ldw, const double* R2, int ldr2,
 // mapped for the device, so the host reads them without a copy.  stop (may
 // be NULL, device): when *stop is set the tail does nothing; a tail that
 // ends the cycle sets it (for steps queued ahead of the host's checks).
+// seq > 0 (with host_ctrl): written last to host_ctrl[kSeqWord], after a
+// system-scope fence, so the host can wait for the tail by polling that
+// word instead of an event or a stream query.
+constexpr int kSeqWord = 16;
 size_t block_tail_scratch_doubles(int nb_max, int s_max);
 void block_tail(const double* W, const double* R2, int ldw, const double* Z,
                 const double* Zt, const double* Zi, const double* Zti, int ldz,
@@ -402,7 +415,7 @@ void block_tail(const double* W, const double* R2, int ldw, const double* Z,
                 double* Hr, int ldh, double* cs, double* sn, double* g,
                 const double* rec, int n_rec, const double* beta0, double tol,
                 double* res_out, int* host_ctrl, double* scratch,
-                hipStream_t st, int* stop = nullptr);
+                hipStream_t st, int* stop = nullptr, int seq = 0);
 void back_solve(const double* Hr, int ldh, const double* g, const int* kdev,
                 int kmax, double* y, hipStream_t st);
 void givens_init(double* g, int m, const double* beta, hipStream_t st);

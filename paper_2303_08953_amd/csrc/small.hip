@@ -19,14 +19,50 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
+// Inputs the short forms below take: far from underflow and overflow.
+__device__ __forceinline__ bool in_range(double x) {
+  return x >= 1e-290 && x <= 1e290;
+}
+
+// 1 / sqrt(x) for x in range: the hardware estimate refined by two Newton
+// steps y <- y + y (1 - x y^2) / 2 (a few units of roundoff; the latency
+// of a few multiply-adds instead of a correctly rounded square root and a
+// division).
+__device__ __forceinline__ double rsqrt_f64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-(x * y), y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 // Largest eigenvalue of [[a, b], [b, c]] and a unit eigenvector (u, v).
+// With d = (a - c) / 2 and r = sqrt(d^2 + b^2): lam = (a + c) / 2 + r, and
+// the eigenvector is proportional to (|d| + r, b) when a >= c, to
+// (b, |d| + r) otherwise; its square norm is 2 r (|d| + r).
 __device__ void top_eig_2x2(double a, double b, double c, double& lam,
                             double& u, double& v) {
-  lam = 0.5 * (a + c) + hypot(0.5 * (a - c), b);
   if (b == 0.0) {
+    lam = 0.5 * (a + c) + fabs(0.5 * (a - c));
     if (a >= c) { u = 1.0; v = 0.0; } else { u = 0.0; v = 1.0; }
     return;
   }
+  const double d = 0.5 * (a - c);
+  const double q = fma(d, d, b * b);
+  const double r = q * rsqrt_f64(q);
+  const double e = fabs(d) + r;
+  const double n2 = 2.0 * r * e;
+  if (in_range(q) && in_range(n2)) {
+    lam = 0.5 * (a + c) + r;
+    const double rn = rsqrt_f64(n2);
+    const double x = e * rn, y = b * rn;
+    if (a >= c) { u = x; v = y; } else { u = y; v = x; }
+    return;
+  }
+  // scaled forms near underflow or overflow
+  lam = 0.5 * (a + c) + hypot(d, b);
   double x, y;
   if (a >= c) { x = lam - c; y = b; } else { x = b; y = lam - a; }
   const double nr = hypot(x, y);
@@ -61,12 +97,13 @@ constexpr int kPcholLds = 140 * 1024 / 8;
 constexpr int kPcholMaxS = 256;
 
 // Estimator step of column j (all lanes of the calling wavefront): from the
-// pivot and the running sums of column j, update (smax2, dn2) and publish
-// the step in est[0..7]: rjj, 1/rjj, s1, c1, s2, c2, d_j, stop (0/1).
-__device__ __forceinline__ void ice_step(int j, double piv, double a,
+// pivot and the running sums of column j, update (smax2, dn2) and return
+// the step in e[0..7]: rjj, 1/rjj, s1, c1, s2, c2, d_j, stop (0/1); the
+// same on every lane.
+__device__ __forceinline__ void ice_eval(int j, double piv, double a,
                                          double a2, double omega,
                                          double& smax2, double& dn2,
-                                         double* est) {
+                                         double* e) {
   const int lane = threadIdx.x % kWave;
   double stop = 0.0;
   double rjj = 0.0, rinv = 0.0, s1 = 0.0, c1 = 1.0, s2 = 0.0, c2 = 1.0;
@@ -74,9 +111,15 @@ __device__ __forceinline__ void ice_step(int j, double piv, double a,
   if (!(piv > 0.0) || !isfinite(piv)) {
     stop = 1.0;
   } else {
-    rjj = sqrt(piv);
-    rinv = 1.0 / rjj;
-    double kappa = 1.0;
+    if (in_range(piv)) {
+      rinv = rsqrt_f64(piv);
+      rjj = piv * rinv;
+    } else {
+      rjj = sqrt(piv);
+      rinv = 1.0 / rjj;
+    }
+    // kappa^2 = smax2 dn2 against omega^2 (no square root on the chain)
+    double kappa2 = 1.0;
     const double r2 = rjj * rjj;
     if (j == 0) {
       smax2 = r2;
@@ -97,21 +140,31 @@ __device__ __forceinline__ void ice_step(int j, double piv, double a,
       dn2 = readlane_f64(lam, 1);
       s2 = readlane_f64(u, 1);
       c2 = readlane_f64(v, 1);
-      kappa = sqrt(smax2 * dn2);
+      kappa2 = smax2 * dn2;
     }
-    if (!(kappa <= omega)) stop = 1.0;
+    if (!(kappa2 <= omega * omega)) stop = 1.0;
     dj = (c2 - s2 * a2) * rinv;
   }
-  if (lane == 0) {
-    est[0] = rjj;
-    est[1] = rinv;
-    est[2] = s1;
-    est[3] = c1;
-    est[4] = s2;
-    est[5] = c2;
-    est[6] = dj;
-    est[7] = stop;
-  }
+  e[0] = rjj;
+  e[1] = rinv;
+  e[2] = s1;
+  e[3] = c1;
+  e[4] = s2;
+  e[5] = c2;
+  e[6] = dj;
+  e[7] = stop;
+}
+
+// The same, published in est[0..7] (LDS) for the other wavefronts.
+__device__ __forceinline__ void ice_step(int j, double piv, double a,
+                                         double a2, double omega,
+                                         double& smax2, double& dn2,
+                                         double* est) {
+  double e[8];
+  ice_eval(j, piv, a, a2, omega, smax2, dn2, e);
+  if (threadIdx.x % kWave == 0)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) est[k] = e[k];
 }
 
 // The body is instantiated twice: with the LDS array (every access then
@@ -129,9 +182,21 @@ __device__ __forceinline__ void pchol_body(
   // one LDS bank
   const int lri = s + 1;
   double* Ri = Aw + (size_t)s * s;
-  for (int e = tid; e < s * s; e += nthr) {
-    const int i = e % s, j = e / s;  // G symmetric: (i, j) -> row i, col j
-    Aw[i * la + j] = G[(int64_t)j * ldg + i];
+  // G symmetric: (i, j) -> row i, col j; eight loads in flight per thread
+  for (int e0 = tid; e0 < s * s; e0 += 8 * nthr) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + q * nthr;
+      const int i = e % la, j = e / la;
+      v[q] = e < s * s ? G[(int64_t)j * ldg + i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = e0 + q * nthr;
+      const int i = e % la, j = e / la;
+      if (e < s * s) Aw[i * la + j] = v[q];
+    }
   }
   double P = 0.0, Q = 0.0;        // estimator sums of column tid
   double smax2 = 0.0, dn2 = 0.0;  // estimator state (wavefront 0)
@@ -371,6 +436,7 @@ __device__ __forceinline__ void tile_gemm_mfma(int m, int n, int k,
 // owning whole columns.  A breakdown (p2 = 0) yields one column with a zero
 // subdiagonal.
 constexpr int kTailLds = 150 * 1024 / 8;
+constexpr int kTailMaxP = 256;  // largest block
 
 // doubles of the work area:
 //   Rt_top nb*p | Rkk p*p | Tinv p*p | union(R2 nb*p, Z, Zt, Zi, Zti p*p
@@ -396,7 +462,8 @@ __device__ __forceinline__ void tail_body(
     double* __restrict__ cs, double* __restrict__ sn, double* __restrict__ g,
     const double* __restrict__ rec, int n_rec,
     const double* __restrict__ beta0, double tol,
-    double* __restrict__ res_out, int* __restrict__ host_ctrl, int* stop) {
+    double* __restrict__ res_out, int* __restrict__ host_ctrl, int* stop,
+    int seq, double* recs) {
   int& kdone_s = sh[0];
   int& conv_s = sh[1];
   int& bad_s = sh[2];
@@ -421,27 +488,81 @@ __device__ __forceinline__ void tail_body(
   double* css = Hn + (size_t)nr * p;
   double* sns = css + nb;
   double* gs = sns + nb;
-  // 0. stage the inputs (coalesced); Z, Zt, Zi, Zti zero-padded to p x p
-  for (int e = tid; e < nb * p; e += kSmallBlock) {
-    const int r = e % nb, c = e / nb;
-    R2[(size_t)c * nb + r] = c < pz && p1 > 0 ? R2g[(int64_t)c * ldw + r] : 0.0;
-  }
-  for (int e = tid; e < p * p; e += kSmallBlock) {
-    const int r = e % p, c = e / p;
-    const bool in = r < pz && c < pz;
-    const bool in2 = !brk && r < p && c < p;
-    Z[(size_t)c * p + r] = in ? Zg[(int64_t)c * ldz + r] : 0.0;
-    Zt[(size_t)c * p + r] = in2 ? Ztg[(int64_t)c * ldz + r] : 0.0;
-    Zi[(size_t)c * p + r] = in2 ? Zig[(int64_t)c * ldz + r] : 0.0;
-    Zti[(size_t)c * p + r] = in2 ? Ztig[(int64_t)c * ldz + r] : 0.0;
-  }
-  for (int e = tid; e < nb * p; e += kSmallBlock) {
-    const int r = e % nb, c = e / nb;
-    Rt_top[(size_t)c * nb + r] = W[(int64_t)c * ldw + r];
-  }
-  for (int r = tid; r < i0; r += kSmallBlock) {
-    css[r] = cs[r];
-    sns[r] = sn[r];
+  // 0. stage the inputs (coalesced, with a batch of loads in flight per
+  // thread: one global round trip per batch instead of one per element);
+  // Z, Zt, Zi, Zti zero-padded to p x p; the recurrence records of the p
+  // new columns
+  {
+    const int nbp = nb * p;
+    for (int e0 = tid; e0 < nbp; e0 += 8 * kSmallBlock) {
+      double v[8], u[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = e0 + q * kSmallBlock;
+        const int r = e % nb, c = e / nb;
+        const bool in = e < nbp;
+        v[q] = in && c < pz && p1 > 0 ? R2g[(int64_t)c * ldw + r] : 0.0;
+        u[q] = in ? W[(int64_t)c * ldw + r] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int e = e0 + q * kSmallBlock;
+        const int r = e % nb, c = e / nb;
+        if (e < nbp) {
+          R2[(size_t)c * nb + r] = v[q];
+          Rt_top[(size_t)c * nb + r] = u[q];
+        }
+      }
+    }
+    const int pp = p * p;
+    for (int e0 = tid; e0 < pp; e0 += 4 * kSmallBlock) {
+      double z[4], zt[4], zi[4], zti[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + q * kSmallBlock;
+        const int r = e % p, c = e / p;
+        const bool in = e < pp && r < pz && c < pz;
+        const bool in2 = e < pp && !brk;
+        const int64_t o = (int64_t)c * ldz + r;
+        z[q] = in ? Zg[o] : 0.0;
+        zt[q] = in2 ? Ztg[o] : 0.0;
+        zi[q] = in2 ? Zig[o] : 0.0;
+        zti[q] = in2 ? Ztig[o] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = e0 + q * kSmallBlock;
+        if (e < pp) {
+          Z[e] = z[q];
+          Zt[e] = zt[q];
+          Zi[e] = zi[q];
+          Zti[e] = zti[q];
+        }
+      }
+    }
+    for (int r0 = tid; r0 < i0; r0 += 4 * kSmallBlock) {
+      double c4[4], s4[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + q * kSmallBlock;
+        c4[q] = r < i0 ? cs[r] : 0.0;
+        s4[q] = r < i0 ? sn[r] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + q * kSmallBlock;
+        if (r < i0) {
+          css[r] = c4[q];
+          sns[r] = s4[q];
+        }
+      }
+    }
+    for (int j = tid; j < p; j += kSmallBlock) {
+      const int q = j % n_rec;
+      recs[3 * j] = rec[3 * q];
+      recs[3 * j + 1] = rec[3 * q + 1];
+      recs[3 * j + 2] = rec[3 * q + 2];
+    }
   }
   if (tid == 0) {
     ctrl[C_PH] = p;
@@ -472,6 +593,7 @@ __device__ __forceinline__ void tail_body(
       v = 1.0;
     } else {
       double acc = 0.0;
+#pragma unroll 8
       for (int t = 0; t < p - 1; ++t)
         acc += Rt_top[(size_t)t * nb + i0] * Tinv[(size_t)c * p + 1 + t];
       v = -acc;
@@ -487,8 +609,7 @@ __device__ __forceinline__ void tail_body(
   // 2. M = Rt B (tridiagonal B from the records), then M(1:nb, 2:p) -= H X
   for (int e = tid; e < nr * p; e += kSmallBlock) {
     const int r = e % nr, j = e / nr;
-    const int q = j % n_rec;
-    const double th = rec[3 * q], ga = rec[3 * q + 1], de = rec[3 * q + 2];
+    const double th = recs[3 * j], ga = recs[3 * j + 1], de = recs[3 * j + 2];
     double m = th * Rt(r, j) + ga * Rt(r, j + 1);
     if (j >= 1) m += de * Rt(r, j - 1);
     Mb[(size_t)j * nr + r] = m;
@@ -606,10 +727,19 @@ __device__ __forceinline__ void tail_body(
     ctrl[C_KDONE] = kdone;
     ctrl[C_CONV] = conv_s;
     ctrl[C_BAD] = bad_s;
+    // the gate of matrix powers steps queued for the next block
+    ctrl[C_GO] = (brk || conv_s || bad_s) ? -1 : p2;
     // the control words the host needs, straight into its mapped memory
     if (host_ctrl)
       for (int k = 0; k < C_NCTRL; ++k) host_ctrl[k] = ctrl[k];
     if (stop && (brk || conv_s || bad_s)) *stop = 1;
+    // then the sequence word, once the estimates and control words (all
+    // written by this thread) are visible to the host
+    if (host_ctrl && seq > 0) {
+      __threadfence_system();
+      __hip_atomic_store(host_ctrl + kSeqWord, seq, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_SYSTEM);
+    }
   }
 }
 
@@ -623,8 +753,9 @@ __global__ __launch_bounds__(kSmallBlock) void k_block_tail(
     double* __restrict__ sn, double* __restrict__ g,
     const double* __restrict__ rec, int n_rec,
     const double* __restrict__ beta0, double tol, double* __restrict__ res_out,
-    int* __restrict__ host_ctrl, double* scratch, int* stop) {
+    int* __restrict__ host_ctrl, double* scratch, int* stop, int seq) {
   __shared__ double lds[kTailLds];
+  __shared__ double recs[3 * kTailMaxP];  // records of the new columns
   __shared__ int sh[4];
   // a queued step after the end of the cycle: leave every state untouched
   // (the flag was written by an earlier kernel of the stream)
@@ -633,11 +764,11 @@ __global__ __launch_bounds__(kSmallBlock) void k_block_tail(
   if (tail_doubles(nb, p) <= (size_t)kTailLds)
     tail_body(lds, sh, W, R2g, ldw, Zg, Ztg, Zig, Ztig, ldz, nb, ctrl,
               Rtop_out, Rkk_out, Hraw, Hr, ldh, cs, sn, g, rec, n_rec, beta0,
-              tol, res_out, host_ctrl, stop);
+              tol, res_out, host_ctrl, stop, seq, recs);
   else
     tail_body(scratch, sh, W, R2g, ldw, Zg, Ztg, Zig, Ztig, ldz, nb, ctrl,
               Rtop_out, Rkk_out, Hraw, Hr, ldh, cs, sn, g, rec, n_rec, beta0,
-              tol, res_out, host_ctrl, stop);
+              tol, res_out, host_ctrl, stop, seq, recs);
 }
 
 // y = Hr(0:k, 0:k)^{-1} g(0:k), column-oriented back substitution.
@@ -756,11 +887,11 @@ void block_tail(const double* W, const double* R2, int ldw, const double* Z,
                 double* Hr, int ldh, double* cs, double* sn, double* g,
                 const double* rec, int n_rec, const double* beta0, double tol,
                 double* res_out, int* host_ctrl, double* scratch,
-                hipStream_t st, int* stop) {
+                hipStream_t st, int* stop, int seq) {
   hipLaunchKernelGGL(k_block_tail, dim3(1), dim3(kSmallBlock), 0, st, W, R2,
                      ldw, Z, Zt, Zi, Zti, ldz, nb, ctrl, Rtop, Rkk, Hraw, Hr,
                      ldh, cs, sn, g, rec, n_rec, beta0, tol, res_out,
-                     host_ctrl, scratch, stop);
+                     host_ctrl, scratch, stop, seq);
   SGM_CHECK_LAUNCH();
 }
 

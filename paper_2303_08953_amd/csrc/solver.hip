@@ -5,6 +5,7 @@
 // caller's workspace and reads back the accepted block size and the
 // convergence flags once per block.
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -131,7 +132,7 @@ void layout(Arena& a, Work& w, int64_t n, int64_t sell_nnz, int m, int smax,
   w.pchol_scr = a.take<double>(2 * ss + 2 * smax);
   w.tail_scr = a.take<double>((int64_t)block_tail_scratch_doubles(m + 1, smax));
   w.scal = a.take<double>(8);
-  w.ctrl = a.take<int>(C_NCTRL + 1);
+  w.ctrl = a.take<int>(kCtrlWords);
   w.info = a.take<int>(8);
 }
 
@@ -170,6 +171,35 @@ void wait_stream(hipStream_t st) {
     }
   }
 }
+
+// Wait for the block tail with sequence number seq by polling the word it
+// writes last into the mapped host memory.  (An event recorded behind the
+// tail would do, but each event in the stream leaves the GPU idle for a
+// few microseconds between kernels.)  Now and then the stream is queried,
+// so that a failed launch ends the wait with its error.
+void wait_seq(const int* word, int seq, hipStream_t st) {
+  for (uint64_t it = 1;; ++it) {
+    if (__atomic_load_n(word, __ATOMIC_ACQUIRE) == seq) return;
+    if ((it & 1023) == 0) {
+      const hipError_t e = hipStreamQuery(st);
+      if (e == hipSuccess) {
+        if (__atomic_load_n(word, __ATOMIC_ACQUIRE) == seq) return;
+        throw Error{SGM_EHIP, "block tail ended without its sequence word"};
+      }
+      if (e != hipErrorNotReady) {
+        (void)hipGetLastError();
+        throw Error{SGM_EHIP, std::string("stream: ") + hipGetErrorString(e)};
+      }
+    }
+  }
+}
+
+// Matrix powers steps of the next block queued behind a block's tail,
+// before the host has read the tail's result (the block size they assume
+// is the one just used; gated on the device, see C_GO).  While the GPU
+// runs them the host reads the result and queues the rest of the block,
+// so the stream does not run dry once per block.
+constexpr int kSpecSteps = 4;
 
 struct Handle {
   Matrix* M = nullptr;
@@ -314,9 +344,17 @@ struct Engine {
   const sgm_opts& o;
   Shifts sh;
   Result& res;
-  hipEvent_t ev[4];
+  // Per block two events: the start and the end of its matrix powers steps
+  // (two sets in turn: block k uses set k % 2).  A block's
+  // orthogonalisation and tail take the time from its last step to the
+  // next block's first; the cycle's last block ends at ecyc.
+  hipEvent_t em0[2], em1[2], ecyc;
+  int last = 1;             // set of the last block
+  bool orth_open = false;   // a block of this cycle has run
+  bool orth_pending = false;  // ecyc recorded, the last block's time unread
+  int seq = 0;              // sequence number of the last block tail
   MpkPlan mplan;
-  std::vector<MpkStep> msteps;
+  std::vector<MpkStep> msteps, spec_steps;
   const Ilu* ilu = nullptr;  // right ILU(0) preconditioner (float64 only)
 
   Engine(const Matrix& A_, const Sell& S_, const T* v, const double* v64,
@@ -327,13 +365,32 @@ struct Engine {
     const bool f32 = sizeof(T) == 4;
     omega = o.omega > 0 ? o.omega : default_omega(f32);
     eps = unit_roundoff(f32);
-    for (auto& e : ev) SGM_HIP(hipEventCreate(&e));
+    for (auto& e : em0) SGM_HIP(hipEventCreate(&e));
+    for (auto& e : em1) SGM_HIP(hipEventCreate(&e));
+    SGM_HIP(hipEventCreate(&ecyc));
+    // earlier solves on this handle have finished: continue their sequence
+    seq = std::max(0, __atomic_load_n(hm.ctrl + kSeqWord, __ATOMIC_ACQUIRE));
     mplan = mpk_plan(S, A.bandwidth, o.mpk_depth, (int)sizeof(T));
     res.mpk_depth = mplan.depth;
     res.mpk_slab_rows = mplan.depth > 1 ? mplan.slab_slices * kSlice : 0;
   }
   ~Engine() {
-    for (auto& e : ev) (void)hipEventDestroy(e);
+    for (auto& e : em0) (void)hipEventDestroy(e);
+    for (auto& e : em1) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(ecyc);
+  }
+
+  // The last block's orthogonalisation time of the previous cycle (the
+  // stream is idle when this runs: after the true residual).
+  void flush_timing() {
+    if (orth_pending) {
+      SGM_HIP(hipEventSynchronize(ecyc));
+      float to = 0;
+      SGM_HIP(hipEventElapsedTime(&to, em1[last], ecyc));
+      res.t[3] += to;
+      orth_pending = false;
+    }
+    orth_open = false;
   }
 
   // the basis Q(:, 0 : m+1) in 64-row panels of w.qcols columns
@@ -422,44 +479,73 @@ struct Engine {
     }
   }
 
-  // One s-step block: MPK, BCGS2 + partial CholQR2, Hessenberg recovery,
-  // Givens and the convergence test; one host synchronisation at the end.
-  BlockOut block(int nb, int s_eff, bool mono, const double* beta0,
-                 double tol) {
-    const double* rec = mono ? w.mono : w.rec;
+  // The matrix powers steps of a block of s_eff columns from column nb.
+  void make_steps(int nb, int s_eff, bool mono, std::vector<MpkStep>& out) {
     const int nrec = mono ? 1 : sh.n_rec;
-    SGM_HIP(hipEventRecord(ev[0], st));
-    msteps.resize(s_eff);
+    out.resize(s_eff);
     for (int j = 0; j < s_eff; ++j) {
       const int q = j % nrec;
       const double delta = mono ? 0.0 : sh.rec[3 * q + 2];
       const int jprev = (j >= 1 && delta != 0.0) ? nb - 2 + j : -1;
-      msteps[j] = MpkStep{nb - 1 + j, jprev, nb + j, q};
+      out[j] = MpkStep{nb - 1 + j, jprev, nb + j, q};
     }
+  }
+
+  // One s-step block: MPK, BCGS2 + partial CholQR2, Hessenberg recovery,
+  // Givens and the convergence test; one host synchronisation at the end.
+  // The first `pre` matrix powers steps were queued by the previous block
+  // (and found valid).  With spec_s > 0 the first steps of the next block
+  // (spec_s columns from nb + s_eff, as if all s_eff columns are accepted)
+  // are queued behind the tail before the host waits.
+  BlockOut block(int nb, int s_eff, bool mono, const double* beta0,
+                 double tol, int pre = 0, int spec_s = 0) {
+    const double* rec = mono ? w.mono : w.rec;
+    const int nrec = mono ? 1 : sh.n_rec;
+    // this block's events; with steps queued ahead, their start event
+    const int cur = last ^ 1;
+    if (pre == 0) SGM_HIP(hipEventRecord(em0[cur], st));
+    make_steps(nb, s_eff, mono, msteps);
     if (ilu != nullptr) {
       for (int j = 0; j < s_eff; ++j) mpk_step_prec(msteps[j], rec);
     } else {
-      spmv_mpk_steps<T>(S, vals, Q(), msteps.data(), s_eff, rec, mplan, st);
+      spmv_mpk_steps<T>(S, vals, Q(), msteps.data() + pre, s_eff - pre, rec,
+                        mplan, st);
     }
-    SGM_HIP(hipEventRecord(ev[1], st));
+    SGM_HIP(hipEventRecord(em1[cur], st));
     orth_block<T>(Q(), ld, nb, s_eff, omega, w, st, false,
                   o.orth == SGM_ORTH_BCGS2_PYTH);
-    SGM_HIP(hipEventRecord(ev[2], st));
+    seq = seq >= INT_MAX - 1 ? 1 : seq + 1;
     block_tail(w.W, w.R2, w.ldw, w.Z, w.Zt, w.Zinv, w.Ztinv, w.lds, nb,
                w.ctrl, nullptr, nullptr, w.Hraw, w.Hr, w.ldh, w.cs, w.sn, w.g,
-               rec, nrec, beta0, tol, hm.dres, hm.dctrl, w.tail_scr, st);
-    SGM_HIP(hipEventRecord(ev[3], st));
-    wait_stream(st);
-    float t01 = 0, t12 = 0, t23 = 0;
-    SGM_HIP(hipEventElapsedTime(&t01, ev[0], ev[1]));
-    SGM_HIP(hipEventElapsedTime(&t12, ev[1], ev[2]));
-    SGM_HIP(hipEventElapsedTime(&t23, ev[2], ev[3]));
-    res.t[2] += t01;
-    res.t[3] += t12;
-    res.t[4] += t23;
-    // the MPK launches run back to back between ev[0] and ev[1]
-    res.t_spmv += t01;
+               rec, nrec, beta0, tol, hm.dres, hm.dctrl, w.tail_scr, st,
+               nullptr, seq);
+    if (spec_s > 0) {
+      // the next block's first steps, gated on this block's result; they
+      // start the next block's event set
+      make_steps(nb + s_eff, spec_s, mono, spec_steps);
+      SGM_HIP(hipEventRecord(em0[cur ^ 1], st));
+      const int k = std::min(kSpecSteps, spec_s);
+      for (int j = 0; j < k; ++j)
+        spmv_mpk<T>(S, vals, Q(), spec_steps[j].xcol, spec_steps[j].pcol,
+                    spec_steps[j].ycol, rec, spec_steps[j].j, st,
+                    w.ctrl + C_GO, s_eff);
+    }
+    wait_seq(hm.ctrl + kSeqWord, seq, st);
+    // the matrix powers steps of this block (with those queued ahead, and
+    // any wait for the host between them), then the previous block's
+    // orthogonalisation and tail
+    float tm = 0;
+    SGM_HIP(hipEventElapsedTime(&tm, em0[cur], em1[cur]));
+    res.t[2] += tm;
+    res.t_spmv += tm;
     res.n_spmv += s_eff;
+    if (orth_open) {
+      float to = 0;
+      SGM_HIP(hipEventElapsedTime(&to, em1[last], em0[cur]));
+      res.t[3] += to;
+    }
+    orth_open = true;
+    last = cur;
     BlockOut b;
     b.p2 = hm.ctrl[C_P2];
     b.ph = hm.ctrl[C_PH];
@@ -517,11 +603,12 @@ struct Engine {
   // y in w.y.  res_scale converts the estimates to the caller's reference.
   int cycle(const double* beta_dev, const double* beta0_dev, double tol,
             bool prephase_only, double res_scale, bool* conv_out) {
+    flush_timing();
     SGM_HIP(hipMemsetAsync(w.Hraw, 0, sizeof(double) * w.ldh * m, st));
     givens_init(w.g, m, beta_dev, st);
     const int m0 = sh.known ? 0 : std::min(o.s_max, m);
     const int last = prephase_only ? m0 : m;
-    int nb = 1, k = 0;
+    int nb = 1, k = 0, pre = 0;
     bool conv = false;
     int s = sh.s_init;
     // pre-phase block size: 1 (column-wise), or adaptive monomial blocks
@@ -562,7 +649,12 @@ struct Engine {
     }
     while (nb <= last && !conv) {
       if (!sh.known && nb > m0) {
-        compute_shifts(nb - 1);
+        if (orth_open) {
+          SGM_HIP(hipEventRecord(ecyc, st));
+          orth_pending = true;
+        }
+        compute_shifts(nb - 1);  // waits for the stream
+        flush_timing();
         s = sh.s_init;
         res.t[1] += ms_since(t_pre);
         timing_pre = false;
@@ -571,8 +663,14 @@ struct Engine {
       const int s_eff = in_pre ? std::min(std::min(s_pre, m0 + 1 - nb),
                                           m + 1 - nb)
                                : std::min(s, m + 1 - nb);
+      // the next block's size if every column of this one is accepted
+      int spec_s = 0;
+      if (!in_pre && !prephase_only && ilu == nullptr && mplan.depth <= 1 &&
+          nb + s_eff <= last)
+        spec_s = std::min(s_eff, m + 1 - (nb + s_eff));
       BlockOut b = block(nb, s_eff, in_pre || o.basis == SGM_BASIS_MONOMIAL,
-                         beta0_dev, prephase_only ? -1.0 : tol);
+                         beta0_dev, prephase_only ? -1.0 : tol, pre, spec_s);
+      pre = 0;
       if (b.bad) throw Error{SGM_ENUMERIC, "non-finite residual estimate"};
       if (!prephase_only) {
         for (int j = 0; j < b.kdone; ++j)
@@ -589,6 +687,14 @@ struct Engine {
       nb += b.p2;
       if (!in_pre) s = b.p2;
       else if (o.prephase == SGM_PREPHASE_MONOMIAL) s_pre = b.p2;
+      // the steps queued ahead are the next block's when all s_eff columns
+      // were accepted and the cycle goes on (the device gate agrees)
+      if (spec_s > 0 && !b.brk && !b.conv && !b.bad && b.p2 == s_eff)
+        pre = std::min(kSpecSteps, spec_s);
+    }
+    if (orth_open) {
+      SGM_HIP(hipEventRecord(ecyc, st));
+      orth_pending = true;
     }
     if (!sh.known) {
       compute_shifts(k);
@@ -680,6 +786,7 @@ void run_solve(Handle* h, const double* b, const double* x0, double* x,
   auto finish = [&]() {
     if (jac) vec_scale_div(x, A.diag, n, true, st);
     wait_stream(st);
+    E.flush_timing();
     R.t[7] = ms_since(t0);
   };
   if (beta0 == 0.0) {
@@ -885,7 +992,7 @@ void block_layout(Arena& a, Work& w, int i, int s, int64_t n_rows) {
   w.Ztinv = a.take<double>(ss);
   w.Rkk = a.take<double>(ss);
   w.pchol_scr = a.take<double>(2 * ss + 2 * s);
-  w.ctrl = a.take<int>(C_NCTRL + 1);
+  w.ctrl = a.take<int>(kCtrlWords);
 }
 
 // ------------------------------------------------------- static scratch
@@ -941,7 +1048,7 @@ void block_layout_static(Arena& a, Work& w, int i, int s) {
   w.Ztinv = a.take<double>(ss);
   w.Rkk = a.take<double>(ss);
   w.pchol_scr = a.take<double>(2 * ss + 2 * s);
-  w.ctrl = a.take<int>(C_NCTRL + 1);
+  w.ctrl = a.take<int>(kCtrlWords);
   a.off = (size_t)round_up((int64_t)a.off, 256);
   const int64_t left =
       ((int64_t)(kStaticScratchDoubles * sizeof(double)) - (int64_t)a.off) /

@@ -93,9 +93,14 @@ __device__ __forceinline__ T mpk_row(T sum, T xo, T xp, bool has_prev,
 // x, xprev and y are columns of a block of vectors with layout XV (row r of
 // a column at column base + XV.row_off(r)); the plain and residual
 // epilogues use contiguous vectors (column-major view).  The matrix
-// multiplies xm with layout XM: x itself, or with a right preconditioner
-// z = M^{-1} x while the recurrence's shift terms still use x.
-template <typename T, int EPI, typename IDX>
+// multiplies x itself, or (PREC) xm with layout XM: with a right
+// preconditioner z = M^{-1} x while the recurrence's shift terms still use
+// x.  GATED: the launch does nothing unless *gate == expect.  Both are
+// separate instantiations: the few extra argument loads and waits at the
+// start of every wavefront cost the other launches 3-5% on a 7-point
+// stencil, whose wavefronts are short.
+template <typename T, int EPI, typename IDX, bool GATED = false,
+          bool PREC = false>
 __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
     const int64_t* __restrict__ ptr, const int32_t* __restrict__ width,
     const IDX* __restrict__ col, const int32_t* __restrict__ kbase,
@@ -103,7 +108,13 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
     QView<T> XM, const T* __restrict__ xm, const T* __restrict__ xprev,
     T* __restrict__ y, const double* __restrict__ b,
     double* __restrict__ part, int64_t n, int64_t nslices,
-    const double* __restrict__ rec, int j, int xcd_contig) {
+    const double* __restrict__ rec, int j, int xcd_contig,
+    const int* __restrict__ gate, int expect) {
+  // a step queued ahead of the result it depends on: nothing to do unless
+  // the assumed block size was right
+  if constexpr (GATED) {
+    if (*gate != expect) return;
+  }
   // Workgroup b runs on XCD b % 8.  With xcd_contig each XCD takes one
   // contiguous range of slices instead of every eighth group of four, so
   // the x lines that neighbouring slices share are fetched into one L2.
@@ -133,8 +144,13 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
   } else if constexpr (EPI == EPI_RESID) {
     if (r < n) bb = b[r];
   }
-  const T sum = sell_row_dot<T, IDX>(ptr, width, col, kbase, val, XM, xm,
-                                     nslices, s, lane);
+  T sum;
+  if constexpr (PREC)
+    sum = sell_row_dot<T, IDX>(ptr, width, col, kbase, val, XM, xm, nslices,
+                               s, lane);
+  else
+    sum = sell_row_dot<T, IDX>(ptr, width, col, kbase, val, XV, x, nslices,
+                               s, lane);
   if constexpr (EPI == EPI_PLAIN) {
     if (r < n) y[r] = sum;
   } else if constexpr (EPI == EPI_MPK) {
@@ -310,7 +326,7 @@ void spmv_plain(const Sell& S, const T* val, const T* x, T* y,
                      colmajor_view<T>(nullptr, 0), x, (const T*)nullptr,      \
                      y, (const double*)nullptr, (double*)nullptr, S.n,        \
                      S.nslices, (const double*)nullptr, 0,                    \
-                     xcd_contig(S, (int)sizeof(T)))
+                     xcd_contig(S, (int)sizeof(T)), (const int*)nullptr, 0)
   if (S.rcol) SGM_SPMV(int16_t, S.rcol); else SGM_SPMV(int32_t, S.col);
 #undef SGM_SPMV
   SGM_CHECK_LAUNCH();
@@ -318,15 +334,23 @@ void spmv_plain(const Sell& S, const T* val, const T* x, T* y,
 
 template <typename T>
 void spmv_mpk(const Sell& S, const T* val, QView<T> Q, int jx, int jprev,
-              int jy, const double* rec, int j, hipStream_t st) {
+              int jy, const double* rec, int j, hipStream_t st,
+              const int* gate, int expect) {
   const T* xp = jprev >= 0 ? (const T*)Q.col(jprev) : (const T*)nullptr;
-#define SGM_SPMV(IDX, colp)                                                   \
-  hipLaunchKernelGGL((k_spmv<T, EPI_MPK, IDX>), dim3(spmv_grid(S)),           \
+#define SGM_SPMV(IDX, G, colp)                                                \
+  hipLaunchKernelGGL((k_spmv<T, EPI_MPK, IDX, G>), dim3(spmv_grid(S)),        \
                      dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, S.kbase,  \
                      val, Q, (const T*)Q.col(jx), Q, (const T*)Q.col(jx), xp, \
                      Q.col(jy), (const double*)nullptr, (double*)nullptr,     \
-                     S.n, S.nslices, rec, j, xcd_contig(S, (int)sizeof(T)))
-  if (S.rcol) SGM_SPMV(int16_t, S.rcol); else SGM_SPMV(int32_t, S.col);
+                     S.n, S.nslices, rec, j, xcd_contig(S, (int)sizeof(T)),  \
+                     gate, expect)
+  if (gate != nullptr) {
+    if (S.rcol) SGM_SPMV(int16_t, true, S.rcol);
+    else SGM_SPMV(int32_t, true, S.col);
+  } else {
+    if (S.rcol) SGM_SPMV(int16_t, false, S.rcol);
+    else SGM_SPMV(int32_t, false, S.col);
+  }
 #undef SGM_SPMV
   SGM_CHECK_LAUNCH();
 }
@@ -418,12 +442,14 @@ void spmv_mpk_prec(const Sell& S, const double* val, QView<double> Q,
   const double* xp =
       jprev >= 0 ? (const double*)Q.col(jprev) : (const double*)nullptr;
 #define SGM_SPMV(IDX, colp)                                                   \
-  hipLaunchKernelGGL((k_spmv<double, EPI_MPK, IDX>), dim3(spmv_grid(S)),      \
+  hipLaunchKernelGGL((k_spmv<double, EPI_MPK, IDX, false, true>),             \
+                     dim3(spmv_grid(S)),                                      \
                      dim3(kSpmvBlock), 0, st, S.ptr, S.width, colp, S.kbase,  \
                      val, Q, (const double*)Q.col(jx),                        \
                      colmajor_view<double>(nullptr, 0), z, xp, Q.col(jy),     \
                      (const double*)nullptr, (double*)nullptr, S.n,           \
-                     S.nslices, rec, j, xcd_contig(S, (int)sizeof(double)))
+                     S.nslices, rec, j, xcd_contig(S, (int)sizeof(double)),  \
+                     (const int*)nullptr, 0)
   if (S.rcol) SGM_SPMV(int16_t, S.rcol); else SGM_SPMV(int32_t, S.col);
 #undef SGM_SPMV
   SGM_CHECK_LAUNCH();
@@ -447,7 +473,7 @@ int64_t spmv_resid(const Sell& S, const double* val, const double* x,
                      val, colmajor_view<double>(nullptr, 0), x,               \
                      colmajor_view<double>(nullptr, 0), x,                    \
                      (const double*)nullptr, r, b, part, S.n, S.nslices,      \
-                     (const double*)nullptr, 0, 0)
+                     (const double*)nullptr, 0, 0, (const int*)nullptr, 0)
   if (S.rcol) SGM_SPMV(int16_t, S.rcol); else SGM_SPMV(int32_t, S.col);
 #undef SGM_SPMV
   SGM_CHECK_LAUNCH();
@@ -459,9 +485,11 @@ template void spmv_plain<double>(const Sell&, const double*, const double*,
 template void spmv_plain<float>(const Sell&, const float*, const float*,
                                 float*, hipStream_t);
 template void spmv_mpk<double>(const Sell&, const double*, QView<double>, int,
-                               int, int, const double*, int, hipStream_t);
+                               int, int, const double*, int, hipStream_t,
+                               const int*, int);
 template void spmv_mpk<float>(const Sell&, const float*, QView<float>, int,
-                              int, int, const double*, int, hipStream_t);
+                              int, int, const double*, int, hipStream_t,
+                              const int*, int);
 
 void reduce_norm(const double* part, int64_t np, double* out,
                  hipStream_t st) {

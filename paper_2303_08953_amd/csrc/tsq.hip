@@ -690,54 +690,76 @@ __global__ __launch_bounds__(kGBlock) void k_gram_wide(
   }
 }
 
-// C(i, j) = sum over chunks of part[c][j * ma + i]; with sym, entries below
-// the diagonal 16x16 tiles are read from the mirrored upper entry.  One
-// workgroup of 16 wavefronts per 64 consecutive outputs: wavefront w sums
-// the chunks c = w, w + 16, ... (lane = output, so every load is a
-// contiguous 64-element run), then the 16 partial sums are added in a fixed
-// order through LDS.  Deterministic.
-constexpr int kRedWaves = 16;
+// Fixed-order sums over the chunks of partial results.  A workgroup of
+// 1024 threads takes kRedOut consecutive outputs: thread t sums output
+// t % kRedOut over the chunks c = g, g + kRedGroups, ... (g = t / kRedOut)
+// with up to 16 loads in flight (one round for up to 1024 chunks; each
+// load instruction reads kRedOut consecutive doubles per chunk), then the
+// kRedGroups sums meet in a fixed LDS tree.  Deterministic.  (One output
+// per lane and 16 chunk groups per workgroup took four dependent load
+// rounds at 512 chunks and a sixteenth of the workgroups.)
+constexpr int kRedThreads = 1024;
+constexpr int kRedOut = 16;
+constexpr int kRedGroups = kRedThreads / kRedOut;
+constexpr int kRedBatch = 16;
 
-__global__ __launch_bounds__(kRedWaves * kWave) void k_reduce_chunks(
+// Sum of part[c * stride + src] over the thread's chunks, in chunk order.
+__device__ __forceinline__ double chunk_sum(const double* __restrict__ part,
+                                            int64_t nchunks, int64_t stride,
+                                            int64_t src, int g) {
+  double s = 0.0;
+  for (int64_t c = g; c < nchunks; c += kRedBatch * kRedGroups) {
+    double a[kRedBatch];
+#pragma unroll
+    for (int q = 0; q < kRedBatch; ++q) {
+      const int64_t cq = c + (int64_t)q * kRedGroups;
+      a[q] = cq < nchunks ? part[cq * stride + src] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < kRedBatch; ++q) s += a[q];
+  }
+  return s;
+}
+
+// red[t] holds thread t's sum; afterwards red[o] (o < kRedOut) holds the
+// total of output o, added over the groups in a fixed tree.
+__device__ __forceinline__ void group_tree(double* red) {
+  const int g = threadIdx.x / kRedOut;
+  __syncthreads();
+#pragma unroll
+  for (int h = kRedGroups / 2; h > 0; h >>= 1) {
+    if (g < h) red[threadIdx.x] += red[threadIdx.x + h * kRedOut];
+    __syncthreads();
+  }
+}
+
+// C(i, j) = sum over chunks of part[c][j * ma + i]; with sym, entries below
+// the diagonal 16x16 tiles are read from the mirrored upper entry.
+__global__ __launch_bounds__(kRedThreads) void k_reduce_chunks(
     const double* __restrict__ part, int64_t nchunks, int ma, int nb,
     double* __restrict__ C, int ldc, int sym) {
-  __shared__ double red[kRedWaves][kWave];
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-  const int64_t e = (int64_t)blockIdx.x * kWave + lane;
+  __shared__ double red[kRedThreads];
+  const int o = threadIdx.x % kRedOut, g = threadIdx.x / kRedOut;
+  const int64_t e = (int64_t)blockIdx.x * kRedOut + o;
   const int64_t ne = (int64_t)ma * nb;
-  const int64_t stride = ne;
+  const int i = (int)(e % ma), j = (int)(e / ma);
   double s = 0.0;
-  int64_t src = e;
   if (e < ne) {
-    const int i = (int)(e % ma), j = (int)(e / ma);
-    if (sym && (i / 16) > (j / 16)) src = (int64_t)i * ma + j;
-    int64_t c = w;
-    // eight loads in flight per lane; the sum keeps the chunk order
-    for (; c + 7 * kRedWaves < nchunks; c += 8 * kRedWaves) {
-      double a[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) a[q] = part[(c + q * kRedWaves) * stride + src];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) s += a[q];
-    }
-    for (; c < nchunks; c += kRedWaves) s += part[c * stride + src];
+    const int64_t src =
+        (sym && (i / 16) > (j / 16)) ? (int64_t)i * ma + j : e;
+    s = chunk_sum(part, nchunks, ne, src, g);
   }
-  red[w][lane] = s;
-  __syncthreads();
-  if (w == 0 && e < ne) {
-    double t = 0.0;
-    for (int q = 0; q < kRedWaves; ++q) t += red[q][lane];
-    const int i = (int)(e % ma), j = (int)(e / ma);
-    C[(int64_t)j * ldc + i] = t;
-  }
+  red[threadIdx.x] = s;
+  group_tree(red);
+  if (g == 0 && e < ne) C[(int64_t)j * ldc + i] = red[o];
 }
 
 void launch_reduce(const double* part, int64_t nchunks, int ma, int nb,
                    double* C, int ldc, int sym, hipStream_t st) {
   const int64_t ne = (int64_t)ma * nb;
-  hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)ceil_div(ne, kWave)),
-                     dim3(kRedWaves * kWave), 0, st, part, nchunks, ma, nb, C,
-                     ldc, sym);
+  hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)ceil_div(ne, kRedOut)),
+                     dim3(kRedThreads), 0, st, part, nchunks, ma, nb, C, ldc,
+                     sym);
   SGM_CHECK_LAUNCH();
 }
 
@@ -1733,9 +1755,8 @@ k_col_update_dots_wide(QView<T> Q, int ma, int vcol,
 }
 
 // Fixed-order sum over the chunks of ne = ndots + norm partials (ndots dot
-// products, then with norm the square sum g).  Sixteen wavefronts split the
-// chunks, lane = output, as in k_reduce_chunks.  live = (pmask == NULL or
-// *pmask > 0).
+// products, then with norm the square sum g), kRedOut outputs at a time as
+// in k_reduce_chunks.  live = (pmask == NULL or *pmask > 0).
 // - With norm: the partial Cholesky of the 1 x 1 Gram g (Alg. 3 with
 //   s = 1: the pivot alone decides, one column's condition estimate is 1):
 //   *p_out = 1, R[0] = sqrt(g), Rinv[0] = 1 / R[0] when live and g > 0 is
@@ -1746,38 +1767,25 @@ k_col_update_dots_wide(QView<T> Q, int ma, int vcol,
 //   the 1 / R[0] just computed instead, and are zero when *p_out = 0 (the
 //   second CGS projection of the normalised vector, from the sums of the
 //   unnormalised one).
-__global__ __launch_bounds__(kRedWaves * kWave) void k_col_finish(
+__global__ __launch_bounds__(kRedThreads) void k_col_finish(
     const double* __restrict__ part, int64_t nchunks, int ndots, int norm,
     const int* __restrict__ pmask, const double* __restrict__ dscale,
     double* __restrict__ dots_out, double* __restrict__ R,
     double* __restrict__ Rinv, int* p_out, int norm_scales) {
-  __shared__ double red[kRedWaves][kWave];
+  __shared__ double red[kRedThreads];
   __shared__ double sums[kColWideMax];
   __shared__ double gsum, gscale;
   __shared__ int gok;
-  const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  const int o = threadIdx.x % kRedOut, g = threadIdx.x / kRedOut;
   const int ne = ndots + norm;
   const bool live = pmask == nullptr || *pmask > 0;
   const double sc = (live && dscale) ? dscale[0] : 1.0;
-  for (int e0 = 0; e0 < ne; e0 += kWave) {
-    const int e = e0 + lane;
-    double s = 0.0;
-    if (e < ne) {
-      int64_t c = w;
-      for (; c + 7 * kRedWaves < nchunks; c += 8 * kRedWaves) {
-        double a[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) a[q] = part[(c + q * kRedWaves) * ne + e];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) s += a[q];
-      }
-      for (; c < nchunks; c += kRedWaves) s += part[c * ne + e];
-    }
-    red[w][lane] = s;
-    __syncthreads();
-    if (w == 0 && e < ne) {
-      double t = 0.0;
-      for (int q = 0; q < kRedWaves; ++q) t += red[q][lane];
+  for (int e0 = 0; e0 < ne; e0 += kRedOut) {
+    const int e = e0 + o;
+    red[threadIdx.x] = e < ne ? chunk_sum(part, nchunks, ne, e, g) : 0.0;
+    group_tree(red);
+    if (g == 0 && e < ne) {
+      const double t = red[o];
       if (e < ndots) {
         if (norm_scales)
           sums[e] = t;
@@ -2356,7 +2364,7 @@ void col_dots(QView<const T> Q, int ma, int vcol, const int* pmask,
                        dim3(kBlock), 0, st, Q, ma, vcol, pmask, npanels,
                        ctiles, chunks, P.buf);
   SGM_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(kRedWaves * kWave), 0, st,
+  hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(kRedThreads), 0, st,
                      (const double*)P.buf, (int64_t)chunks, ma, 0, pmask,
                      dscale, C, (double*)nullptr, (double*)nullptr,
                      (int*)nullptr, 0);
@@ -2374,7 +2382,7 @@ void col_update(QView<T> Q, int ma, int vcol, const double* w,
   hipLaunchKernelGGL(k_col_update<T>, dim3(chunks), dim3(kBlock), lds, st, Q,
                      ma, vcol, w, vscale, pmask, npanels, chunks, P.buf);
   SGM_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(kRedWaves * kWave), 0, st,
+  hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(kRedThreads), 0, st,
                      (const double*)P.buf, (int64_t)chunks, 0, 1, pmask,
                      (const double*)nullptr, (double*)nullptr, R, Rinv,
                      p_out, 0);
@@ -2408,7 +2416,7 @@ bool col_update_dots(QView<T> Q, int ma, int vcol, const double* w,
 #undef SGM_CUD
   }
   SGM_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(kRedWaves * kWave), 0, st,
+  hipLaunchKernelGGL(k_col_finish, dim3(1), dim3(kRedThreads), 0, st,
                      (const double*)P.buf, (int64_t)chunks, ma, 1,
                      (const int*)nullptr, (const double*)nullptr, C, R, Rinv,
                      p_out, 1);
