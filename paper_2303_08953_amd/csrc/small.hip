@@ -19,50 +19,14 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-// Inputs the short forms below take: far from underflow and overflow.
-__device__ __forceinline__ bool in_range(double x) {
-  return x >= 1e-290 && x <= 1e290;
-}
-
-// 1 / sqrt(x) for x in range: the hardware estimate refined by two Newton
-// steps y <- y + y (1 - x y^2) / 2 (a few units of roundoff; the latency
-// of a few multiply-adds instead of a correctly rounded square root and a
-// division).
-__device__ __forceinline__ double rsqrt_f64(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double e = fma(-(x * y), y, 1.0);
-    y = fma(0.5 * y, e, y);
-  }
-  return y;
-}
-
 // Largest eigenvalue of [[a, b], [b, c]] and a unit eigenvector (u, v).
-// With d = (a - c) / 2 and r = sqrt(d^2 + b^2): lam = (a + c) / 2 + r, and
-// the eigenvector is proportional to (|d| + r, b) when a >= c, to
-// (b, |d| + r) otherwise; its square norm is 2 r (|d| + r).
 __device__ void top_eig_2x2(double a, double b, double c, double& lam,
                             double& u, double& v) {
+  lam = 0.5 * (a + c) + hypot(0.5 * (a - c), b);
   if (b == 0.0) {
-    lam = 0.5 * (a + c) + fabs(0.5 * (a - c));
     if (a >= c) { u = 1.0; v = 0.0; } else { u = 0.0; v = 1.0; }
     return;
   }
-  const double d = 0.5 * (a - c);
-  const double q = fma(d, d, b * b);
-  const double r = q * rsqrt_f64(q);
-  const double e = fabs(d) + r;
-  const double n2 = 2.0 * r * e;
-  if (in_range(q) && in_range(n2)) {
-    lam = 0.5 * (a + c) + r;
-    const double rn = rsqrt_f64(n2);
-    const double x = e * rn, y = b * rn;
-    if (a >= c) { u = x; v = y; } else { u = y; v = x; }
-    return;
-  }
-  // scaled forms near underflow or overflow
-  lam = 0.5 * (a + c) + hypot(d, b);
   double x, y;
   if (a >= c) { x = lam - c; y = b; } else { x = b; y = lam - a; }
   const double nr = hypot(x, y);
@@ -111,15 +75,9 @@ __device__ __forceinline__ void ice_eval(int j, double piv, double a,
   if (!(piv > 0.0) || !isfinite(piv)) {
     stop = 1.0;
   } else {
-    if (in_range(piv)) {
-      rinv = rsqrt_f64(piv);
-      rjj = piv * rinv;
-    } else {
-      rjj = sqrt(piv);
-      rinv = 1.0 / rjj;
-    }
-    // kappa^2 = smax2 dn2 against omega^2 (no square root on the chain)
-    double kappa2 = 1.0;
+    rjj = sqrt(piv);
+    rinv = 1.0 / rjj;
+    double kappa = 1.0;
     const double r2 = rjj * rjj;
     if (j == 0) {
       smax2 = r2;
@@ -140,9 +98,9 @@ __device__ __forceinline__ void ice_eval(int j, double piv, double a,
       dn2 = readlane_f64(lam, 1);
       s2 = readlane_f64(u, 1);
       c2 = readlane_f64(v, 1);
-      kappa2 = smax2 * dn2;
+      kappa = sqrt(smax2 * dn2);
     }
-    if (!(kappa2 <= omega * omega)) stop = 1.0;
+    if (!(kappa <= omega)) stop = 1.0;
     dj = (c2 - s2 * a2) * rinv;
   }
   e[0] = rjj;
@@ -660,25 +618,46 @@ __device__ __forceinline__ void tail_body(
         h[i0] = carry;
       }
     }
-    // new rotations in order; g's running entry gcur is uniform
+    // new rotations in order; g's running entry gcur is uniform.  Lane l
+    // keeps, for each of its columns jj = l + 64 q, the entry at the
+    // current rotation row c in cur[q] and the next row's entry in nxt[q]
+    // and the one after in nx2[q] (read two rows ahead from LDS, so the
+    // owner's operands are in registers when its turn comes): rotation
+    // j needs only the owner's two registers, and applying it to a later
+    // column leaves that column's row c final (stored) and its row c + 1
+    // in cur.  The rotation chain per column then holds no LDS round trip.
+    constexpr int NQ = kTailMaxP / kWave;
+    double cur[NQ], nxt[NQ], nx2[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int jj = lane + kWave * q;
+      const bool in = jj < p;
+      cur[q] = in ? Hn[(size_t)jj * nr + i0] : 0.0;
+      nxt[q] = in ? Hn[(size_t)jj * nr + i0 + 1] : 0.0;
+      nx2[q] = in && i0 + 2 < nr ? Hn[(size_t)jj * nr + i0 + 2] : 0.0;
+    }
     double gcur = g[i0];
     const double b0 = beta0[0];
     int kdone = p, conv = 0, bad = 0;
     for (int j = 0; j < p; ++j) {
       const int c = i0 + j;
-      const int owner = j % kWave;
+      const int owner = j % kWave, qo = j / kWave;
       double cc = 1.0, ss = 0.0;
       if (lane == owner) {
-        double* h = Hn + (size_t)j * nr;
-        const double a = h[c], b = h[c + 1];
-        double rr;
-        if (b == 0.0) {
-          rr = a;
-        } else {
+        double a = cur[0], b = nxt[0];
+#pragma unroll
+        for (int q = 1; q < NQ; ++q)
+          if (q == qo) {
+            a = cur[q];
+            b = nxt[q];
+          }
+        double rr = a;
+        if (b != 0.0) {
           rr = hypot(a, b);
           cc = a / rr;
           ss = b / rr;
         }
+        double* h = Hn + (size_t)j * nr;
         h[c] = rr;
         h[c + 1] = 0.0;
       }
@@ -699,12 +678,17 @@ __device__ __forceinline__ void tail_body(
         bad = isfinite(res) ? 0 : 1;
         break;
       }
-      for (int jj = lane; jj < p; jj += kWave) {
-        if (jj <= j) continue;
-        double* h2 = Hn + (size_t)jj * nr;
-        const double a = h2[c], b = h2[c + 1];
-        h2[c] = cc * a + ss * b;
-        h2[c + 1] = -ss * a + cc * b;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int jj = lane + kWave * q;
+        if (jj > j && jj < p) {
+          double* h2 = Hn + (size_t)jj * nr;
+          const double a = cur[q], b = nxt[q];
+          h2[c] = cc * a + ss * b;
+          cur[q] = -ss * a + cc * b;
+          nxt[q] = nx2[q];
+          nx2[q] = c + 3 < nr ? h2[c + 3] : 0.0;
+        }
       }
     }
     if (lane == 0) {
