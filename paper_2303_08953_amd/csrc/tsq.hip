@@ -537,13 +537,14 @@ __global__ __launch_bounds__(kRBlock) void k_gemm_tn_tall(
 // ------------------------------------------------------------- wide Gram
 // G = Q(:, b0:b0+nb)^T Q(:, b0:b0+nb) for Gram matrices of 65 to 256
 // columns.  One 1024-thread workgroup per row chunk loads each 16-row batch
-// of all nb columns into LDS once (double-buffered, column stride 17), and
+// of all nb columns into LDS once (double-buffered, column stride ROWS + 1), and
 // the sixteen wavefronts form the nt (nt + 1) / 2 tiles on and above the
 // diagonal (nt = 16 ceil(nb / 16)) from there: wavefront w takes the
 // contiguous run [T w / 16, T (w + 1) / 16) of them in column order, so
 // consecutive tiles mostly share their B operand, which is read once per
 // column.  Sixteen wavefronts of at most 9 tiles fit four to a SIMD (eight
-// of 17 fitted two): 20.5 -> 15.9 ms for 200 columns over 16.8M rows.
+// of 17 fitted two): 20.5 -> 15.9 ms for 200 columns over 16.8M rows, and
+// 32-row batches with at most 7 tiles (up to 224 columns) 15.6 -> 14.7 ms.
 // The reduction mirrors the lower tiles.  Columns past nb read a
 // valid column (their results are not stored); columns past *ncount give
 // zero (as in the kernels above).  Grid: chunks workgroups, each a
@@ -553,14 +554,19 @@ constexpr int kGWaves = kGBlock / kWave;
 // most tiles per wavefront: 136 tiles on and above the diagonal at nb = 256
 constexpr int kGTiles = (136 + kGWaves - 1) / kGWaves;
 constexpr int kGMaxCols = 256;
+// Rows per batch (ROWS) and the LDS column stride ROWS + 1 (odd: no bank
+// conflicts between the lanes' columns).  32-row batches give each barrier
+// and LDS store round eight MFMA k-steps instead of four; with nine tiles
+// per wavefront the float64 kernel then needs more than 128 registers, so
+// that case keeps 16-row batches.
 
-template <typename T>
+template <typename T, int TILES, int ROWS>
 __global__ __launch_bounds__(kGBlock) void k_gram_wide(
     QView<const T> Q, int b0c, int nb, const int* __restrict__ ncount,
     int64_t nbatches, int chunks, double* __restrict__ part) {
   typedef typename Vec4<T>::type V;
   constexpr int EPV = 16 / (int)sizeof(T);  // elements per 16-byte load
-  constexpr int VPC = 16 / EPV;             // loads per 16-row column batch
+  constexpr int VPC = ROWS / EPV;         // loads per column of a batch
   constexpr int NVT = (kGMaxCols * VPC + kGBlock - 1) / kGBlock;
   typedef T vec_t __attribute__((ext_vector_type(EPV)));
   extern __shared__ char smem_raw[];
@@ -571,7 +577,7 @@ __global__ __launch_bounds__(kGBlock) void k_gram_wide(
   const int nt = (nb + 15) / 16;
   const int ncols = nt * 16;
   const int NV = ncols * VPC;               // loads per batch
-  const int LBUF = ncols * kWStride;        // elements per LDS buffer
+  const int LBUF = ncols * (ROWS + 1);        // elements per LDS buffer
   const int nbe = ncount ? min(nb, *ncount) : nb;
   const int chunk = blockIdx.x;
   const int64_t bt0 = nbatches * chunk / chunks;
@@ -580,7 +586,7 @@ __global__ __launch_bounds__(kGBlock) void k_gram_wide(
   // the upper triangle (wavefront-uniform)
   const int T_all = nt * (nt + 1) / 2;
   const int t0 = T_all * wave / kGWaves, t1 = T_all * (wave + 1) / kGWaves;
-  int tr[kGTiles], tc[kGTiles];
+  int tr[TILES], tc[TILES];
   {
     int c = 0, base = 0;  // tiles of columns < c: base = c (c + 1) / 2
     while (base + c + 1 <= t0) {
@@ -589,7 +595,7 @@ __global__ __launch_bounds__(kGBlock) void k_gram_wide(
     }
     int r = t0 - base;
 #pragma unroll
-    for (int u = 0; u < kGTiles; ++u) {
+    for (int u = 0; u < TILES; ++u) {
       tr[u] = r;
       tc[u] = c;
       if (++r > c) {
@@ -600,12 +606,12 @@ __global__ __launch_bounds__(kGBlock) void k_gram_wide(
   }
   const int cnt = t1 - t0;
 
-  // three register stages in a ring: the loads of batch b + 1 go out two
-  // batches before b + 1 is stored to LDS, so their latency is covered by
-  // the MFMA work of two batches
-  vec_t sA[NVT], sB[NVT], sC[NVT];
+  // two register stages: the loads of batch b + 2 go out while batch b is
+  // formed, and are stored to LDS after it, so their latency is covered by
+  // the MFMA work of a whole batch
+  vec_t sA[NVT], sB[NVT];
   auto gload = [&](int64_t bt, vec_t (&stg)[NVT]) {
-    const T* rb = Q.base + Q.row_off(bt * 16);
+    const T* rb = Q.base + Q.row_off(bt * ROWS);
 #pragma unroll
     for (int q = 0; q < NVT; ++q) {
       const int e = threadIdx.x + kGBlock * q;
@@ -623,42 +629,44 @@ __global__ __launch_bounds__(kGBlock) void k_gram_wide(
     for (int q = 0; q < NVT; ++q) {
       const int e = threadIdx.x + kGBlock * q;
       if (e < NV) {
-        T* d = L + (e / VPC) * kWStride + (e % VPC) * EPV;
+        T* d = L + (e / VPC) * (ROWS + 1) + (e % VPC) * EPV;
 #pragma unroll
         for (int u = 0; u < EPV; ++u) d[u] = stg[q][u];
       }
     }
   };
 
-  V acc[kGTiles];
+  V acc[TILES];
 #pragma unroll
-  for (int u = 0; u < kGTiles; ++u) acc[u] = vzero<V>();
+  for (int u = 0; u < TILES; ++u) acc[u] = vzero<V>();
   auto compute = [&](int buf) {
-    const T* L = lds + buf * LBUF + c16 * kWStride + g;
+    const T* L = lds + buf * LBUF + c16 * (ROWS + 1) + g;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < ROWS / 4; ++q) {
       int cur = -1;
       T bv = 0;
 #pragma unroll
-      for (int u = 0; u < kGTiles; ++u) {
+      for (int u = 0; u < TILES; ++u) {
         if (u < cnt) {
           if (tc[u] != cur) {
             cur = tc[u];
-            bv = L[cur * 16 * kWStride + 4 * q];
+            bv = L[cur * 16 * (ROWS + 1) + 4 * q];
           }
-          acc[u] = mfma(L[tr[u] * 16 * kWStride + 4 * q], bv, acc[u]);
+          acc[u] = mfma(L[tr[u] * 16 * (ROWS + 1) + 4 * q], bv, acc[u]);
         }
       }
     }
   };
   int buf = 0;
   // batch b: compute from LDS, store batch b + 1 (registers `nxt`) to the
-  // other LDS buffer, load batch b + 3 into the registers `fre` that held b
+  // other LDS buffer, load batch b + 2 into the registers `fre` that held
+  // batch b (storing and loading before the MFMA work measured slower: the
+  // store then waits for loads issued only one batch earlier)
   auto step = [&](int64_t b, const vec_t (&nxt)[NVT], vec_t (&fre)[NVT]) {
     if (b >= bt1) return;
     compute(buf);
     if (b + 1 < bt1) lstore(buf ^ 1, nxt);
-    if (b + 3 < bt1) gload(b + 3, fre);
+    if (b + 2 < bt1) gload(b + 2, fre);
     __syncthreads();
     buf ^= 1;
   };
@@ -667,16 +675,14 @@ __global__ __launch_bounds__(kGBlock) void k_gram_wide(
     lstore(0, sA);
   }
   if (bt0 + 1 < bt1) gload(bt0 + 1, sB);
-  if (bt0 + 2 < bt1) gload(bt0 + 2, sC);
   __syncthreads();
-  for (int64_t bt = bt0; bt < bt1; bt += 3) {
+  for (int64_t bt = bt0; bt < bt1; bt += 2) {
     step(bt, sB, sA);
-    step(bt + 1, sC, sB);
-    step(bt + 2, sA, sC);
+    step(bt + 1, sA, sB);
   }
   double* out = part + (int64_t)chunk * nb * nb;
 #pragma unroll
-  for (int u = 0; u < kGTiles; ++u) {
+  for (int u = 0; u < TILES; ++u) {
     if (u < cnt) {
       const int col = tc[u] * 16 + c16;
 #pragma unroll
@@ -1925,18 +1931,30 @@ void gemm_tn(QView<const T> Q, int a0, int ma, int b0, int nb,
     launch_reduce(P.buf, chunks_w, ma, nb, C, ldc, 0, st);
     return;
   }
-  // A Gram matrix of 129 to 256 columns: every 16-row batch of its columns
-  // in LDS once per workgroup, the tiles on and above the diagonal formed
+  // A Gram matrix of 129 to 256 columns: every 32- or 16-row batch of its
+  // columns in LDS once per workgroup, the tiles on and above the diagonal formed
   // from there (the kernels below fetch each operand per wavefront).
-  // Measured in float64: 200 columns over 16.8M rows 15.9 against 33.6 ms;
+  // Measured in float64: 200 columns over 16.8M rows 14.7 against 33.6 ms;
   // at 128 columns over 7.1M rows the kernel below is faster (4.2 against
   // 4.7 ms), so it keeps those.
   if (a0 == b0 && ma == nb && nb > 128 && nb <= kGMaxCols) {
+    // at most 7 tiles per wavefront up to 224 columns (105 tiles): 32-row
+    // batches; 9 up to 256: 16-row batches (the rows past nrows up to the
+    // 64-row panel boundary are zero)
+    const bool seven = nt_all * (nt_all + 1) / 2 <= 7 * kGWaves;
+    const int rows = seven ? 32 : 16;
+    const int64_t gbatches = (nrows + rows - 1) / rows;
     const int chunks_g =
-        pick_chunks(2 * kNumCUs, 1, nbatches, (int64_t)nb * nb, P);
-    const size_t lds = (size_t)2 * nt_all * 16 * kWStride * sizeof(T);
-    hipLaunchKernelGGL(k_gram_wide<T>, dim3(chunks_g), dim3(kGBlock), lds,
-                       st, Q, b0, nb, ncount, nbatches, chunks_g, P.buf);
+        pick_chunks(2 * kNumCUs, 1, gbatches, (int64_t)nb * nb, P);
+    const size_t lds = (size_t)2 * nt_all * 16 * (rows + 1) * sizeof(T);
+    if (seven)
+      hipLaunchKernelGGL((k_gram_wide<T, 7, 32>), dim3(chunks_g),
+                         dim3(kGBlock), lds, st, Q, b0, nb, ncount, gbatches,
+                         chunks_g, P.buf);
+    else
+      hipLaunchKernelGGL((k_gram_wide<T, kGTiles, 16>), dim3(chunks_g),
+                         dim3(kGBlock), lds, st, Q, b0, nb, ncount, gbatches,
+                         chunks_g, P.buf);
     SGM_CHECK_LAUNCH();
     launch_reduce(P.buf, chunks_g, nb, nb, C, ldc, 1, st);
     return;

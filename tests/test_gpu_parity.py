@@ -258,6 +258,33 @@ def test_solve_other_bases(lib, basis):
     assert list(gpu.s_hist) == ref.s_hist
 
 
+def test_solve_partly_accepted_blocks(lib):
+    """Blocks accepted in part (p < s): after each block the solver queues
+    the next block's first matrix powers steps assuming p = s; those launches
+    read the tail's control word and do nothing when p < s or the cycle
+    ends, and the block is queued again in full.  The monomial basis at
+    s_max 10 truncates the first block of every cycle (p = 4 or 5 of 10)
+    and some later ones; the solve must still match the oracle block by
+    block.  Also checks the timing fields of that scheduling."""
+    A = W.conv_diff_2d(32, 10.0)
+    b = W.rhs(A.n, 2)
+    gpu, ref, rel = _compare_solve(lib, A, b, 10, 50, 1e-10,
+                                   basis="monomial")
+    sh = list(ref.s_hist)
+    assert sh[0] < 10                      # the first block is truncated
+    assert any(q < p for p, q in zip(sh, sh[1:])), sh   # and a later one
+    assert list(gpu.s_hist) == sh
+    h, hr = np.array(gpu.res_hist), np.array(ref.res_hist)
+    assert h.size == hr.size
+    assert np.all(np.abs(h - hr) <= 1e-6 * hr + 1e-13)
+    assert rel <= 1e-8
+    i = gpu.info
+    assert i["n_spmv"] >= i["iters"] and i["t_spmv_ms"] > 0.0
+    ph = i["t_phase_ms"]
+    assert ph[2] > 0.0 and ph[3] > 0.0 and ph[4] == 0.0
+    assert ph[2] + ph[3] <= ph[7]
+
+
 def test_solve_ragged_poisson_restarts_x0(lib):
     """n = 27^3 (not a multiple of 64), restarts, nonzero x0."""
     A = W.poisson_3d(27)
