@@ -2179,6 +2179,15 @@ void trsm_inv(QView<T> Q, int b0, int s, const double* Rinv, int ldr,
                                                none, st, 1024);
     return;
   }
+  if (sizeof(T) == 8 && nt == 13) {
+    // 193 to 208 float64 columns, factor packed in LDS: two 16-row tiles
+    // per wavefront and one wavefront per SIMD (256 threads: 512 registers
+    // a lane), so each read of the factor feeds two MFMAs
+    launch_update_b<T, 13, 2, MODE_TRSM, false, 256>(
+        Q, 0, s, b0, s, Rinv, ldr, pcount, nrows, nullptr, 0, none, st,
+        kWideLdsBudget, kNumCUs);
+    return;
+  }
 #define SGM_TR(NTv, MTv)                                                      \
   if (nt == NTv) {                                                            \
     launch_update<T, NTv, MTv, MODE_TRSM, false>(                             \
