@@ -894,22 +894,29 @@ __global__ __launch_bounds__(BLOCK) void k_update(
             // LDS reads at a constant offset.  A column past nce may read
             // another row's value or the padding after the triangle; it
             // only reaches output columns that are never stored.
+            // All NT reads go out together, unconditionally (the tiles
+            // left of the diagonal read entries of earlier rows, rows past
+            // nce the padding after the triangle: all inside the array),
+            // then one wait, then the masks as selects and the MFMAs (a
+            // masked read per tile made every tile wait for its own LDS
+            // round trip).
             const int kp = k0 + kk + g;
             const T* prow = Ms + (kp * nce - kp * (kp - 1) / 2) - kp + c16;
             const int kb = k0 + kk;
             const int jd = kb >> 4;
             const bool tail = kb + 4 > nce;
+            T bv[NT];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) bv[j] = prow[j * 16];
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
               if (kb >= (j + 1) * 16) continue;
-              T bv;
+              T b = bv[j];
               if (j == jd || tail)
-                bv = (j * 16 + c16 >= kp && kp < nce) ? prow[j * 16] : (T)0;
-              else
-                bv = prow[j * 16];
+                b = (j * 16 + c16 >= kp && kp < nce) ? b : (T)0;
 #pragma unroll
               for (int t = 0; t < MT; ++t)
-                acc[t][j] = mfma(a[t], bv, acc[t][j]);
+                acc[t][j] = mfma(a[t], b, acc[t][j]);
             }
           } else {
             const T* mrow = Ms + (kk + g) * W16 + c16;
@@ -917,6 +924,16 @@ __global__ __launch_bounds__(BLOCK) void k_update(
             // past the accepted columns)
             const int kp = k0 + kk + g;
             const T* prow = Ms + (kp * nce - kp * (kp - 1) / 2) - kp;
+            // the staged rows' reads go out together before the MFMAs (a
+            // read after each tile's triangle test waited per tile), where
+            // the registers allow (1024-thread variants of more than 8
+            // tiles would spill)
+            constexpr bool BATCH = !PACKED && (BLOCK <= 512 || NT <= 8);
+            T bs[NT];
+            if constexpr (BATCH) {
+#pragma unroll
+              for (int j = 0; j < NT; ++j) bs[j] = mrow[j * 16];
+            }
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
               if (MODE == MODE_TRSM && (k0 + kk) >= (j + 1) * 16) continue;
@@ -924,6 +941,8 @@ __global__ __launch_bounds__(BLOCK) void k_update(
               if constexpr (PACKED) {
                 const int c = j * 16 + c16;
                 bv = (c >= kp && c < nce && kp < nce) ? prow[c] : (T)0;
+              } else if constexpr (BATCH) {
+                bv = bs[j];
               } else {
                 bv = mrow[j * 16];
               }
