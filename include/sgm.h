@@ -273,6 +273,21 @@ sgm_status sgm_mpk(sgm_matrix A, int transpose, sgm_precision precision,
                    void* Q, int64_t ldq, int32_t c, int32_t s,
                    const double* records, int32_t n_rec, void* stream);
 
+/* sgm_mpk with the fused square-sum epilogue of the matrix powers kernel
+ * (Alg. 4, Eq. (newtonrecurrence)): the same columns, bitwise, and
+ * norms2[j] (device, double[s]) = sum over the rows of Q[:, c+j+1]^2 as
+ * stored (float64 sums, also for SGM_FP32_IR), taken by the SpMV that
+ * forms the column, with no extra pass over Q: the growth of the basis
+ * vectors the paper plots for the monomial and Newton bases.  work
+ * (device, double[work_len], work_len >= ceil(n / 256)) holds the
+ * per-workgroup partial sums of one step at a time; results are
+ * deterministic (fixed summation order).  Other arguments as in sgm_mpk;
+ * NULL norms2 or work, or a shorter work, return SGM_EINVAL when s > 0. */
+sgm_status sgm_mpk_norms(sgm_matrix A, int transpose, sgm_precision precision,
+                         void* Q, int64_t ldq, int32_t c, int32_t s,
+                         const double* records, int32_t n_rec, double* norms2,
+                         double* work, int64_t work_len, void* stream);
+
 /* The matrix powers kernel of sgm_mpk with temporal blocking (the
  * communication-avoiding matrix powers idea of Sec. 2, applied to the
  * cache hierarchy): `depth` (1..4) consecutive steps per pass over the

@@ -95,6 +95,9 @@ _SIGS = [
     ("sgm_mpk", C.c_int,
      [_P, C.c_int, C.c_int, _P, C.c_int64, C.c_int32, C.c_int32, _P,
       C.c_int32, _P]),
+    ("sgm_mpk_norms", C.c_int,
+     [_P, C.c_int, C.c_int, _P, C.c_int64, C.c_int32, C.c_int32, _P,
+      C.c_int32, _P, _P, C.c_int64, _P]),
     ("sgm_mpk_fused", C.c_int,
      [_P, C.c_int, C.c_int, _P, C.c_int64, C.c_int32, C.c_int32, _P,
       C.c_int32, C.c_int32, _P, C.POINTER(C.c_int64)]),
@@ -363,6 +366,23 @@ def mpk(A: Matrix, Q, ldq, c, s, records, transpose=False, precision="fp64",
                          _ptr(Q), int(ldq), int(c), int(s), _ptr(rec),
                          rec.numel() // 3, _stream(stream)))
     torch.cuda.current_stream().synchronize()
+
+
+def mpk_norms(A: Matrix, Q, ldq, c, s, records, transpose=False,
+              precision="fp64", stream=None):
+    """sgm_mpk_norms: sgm_mpk with the fused square-sum epilogue.  Returns
+    the float64 sums of squares of the s new columns (numpy)."""
+    torch = _torch()
+    rec = _dev(np.asarray(records, dtype=np.float64).ravel(), torch.float64)
+    norms2 = torch.zeros(max(1, int(s)), dtype=torch.float64, device="cuda")
+    work = torch.empty((A.n + 255) // 256, dtype=torch.float64,
+                       device="cuda")
+    _check(lib().sgm_mpk_norms(A.handle, int(transpose), PRECISION[precision],
+                               _ptr(Q), int(ldq), int(c), int(s), _ptr(rec),
+                               rec.numel() // 3, _ptr(norms2), _ptr(work),
+                               work.numel(), _stream(stream)))
+    torch.cuda.current_stream().synchronize()
+    return norms2[:int(s)].cpu().numpy()
 
 
 def mpk_fused(A: Matrix, Q, ldq, c, s, records, depth, transpose=False,

@@ -214,6 +214,13 @@ template <typename T>
 void spmv_mpk(const Sell& S, const T* val, QView<T> Q, int jx, int jprev,
               int jy, const double* rec, int j, hipStream_t st,
               const int* gate = nullptr, int expect = 0);
+// The same step with the fused square-sum epilogue: *norm2 = the float64
+// sum of the stored y(r)^2; part holds spmv_grid(S) doubles (the number of
+// SpMV workgroups, resid_partials(S)).
+template <typename T>
+void spmv_mpk_norm(const Sell& S, const T* val, QView<T> Q, int jx, int jprev,
+                   int jy, const double* rec, int j, double* part,
+                   double* norm2, hipStream_t st);
 // The same step with a right preconditioner: y = ((A z) - theta x -
 // delta xprev) / gamma, z = M^{-1} x given as a plain vector (float64).
 void spmv_mpk_prec(const Sell& S, const double* val, QView<double> Q,

@@ -1379,6 +1379,41 @@ sgm_status sgm_mpk(sgm_matrix A, int transpose, sgm_precision precision,
   SGM_API_END
 }
 
+sgm_status sgm_mpk_norms(sgm_matrix A, int transpose, sgm_precision precision,
+                         void* Q, int64_t ldq, int32_t c, int32_t s,
+                         const double* records, int32_t n_rec, double* norms2,
+                         double* work, int64_t work_len, void* stream) {
+  SGM_API_BEGIN
+  SGM_REQUIRE(A != nullptr && Q != nullptr && records != nullptr,
+              "NULL argument");
+  const Matrix& M = *handle(A)->M;
+  SGM_REQUIRE(ldq >= M.n && ldq % kLdAlign == 0,
+              "ldq must be >= n and a multiple of 64");
+  SGM_REQUIRE(c >= 0 && s >= 0 && n_rec >= 1, "bad c/s/n_rec");
+  SGM_REQUIRE(precision == SGM_FP64 || precision == SGM_FP32_IR,
+              "unknown precision");
+  const Sell& S = transpose ? M.trn : M.fwd;
+  SGM_REQUIRE(s == 0 || (norms2 != nullptr && work != nullptr),
+              "NULL norms2 or work");
+  SGM_REQUIRE(s == 0 || work_len >= resid_partials(S),
+              "work must hold ceil(n / 256) doubles");
+  hipStream_t st = as_stream(stream);
+  for (int j = 0; j < s; ++j) {
+    const int q = j % n_rec;
+    const int jprev = j >= 1 ? c + j - 1 : -1;
+    if (precision == SGM_FP64)
+      spmv_mpk_norm<double>(
+          S, S.val64, colmajor_view<double>(static_cast<double*>(Q), ldq),
+          c + j, jprev, c + j + 1, records, q, work, norms2 + j, st);
+    else
+      spmv_mpk_norm<float>(
+          S, S.val32, colmajor_view<float>(static_cast<float*>(Q), ldq),
+          c + j, jprev, c + j + 1, records, q, work, norms2 + j, st);
+  }
+  return SGM_OK;
+  SGM_API_END
+}
+
 sgm_status sgm_mpk_fused(sgm_matrix A, int transpose, sgm_precision precision,
                          void* Q, int64_t ldq, int32_t c, int32_t s,
                          const double* records, int32_t n_rec, int32_t depth,

@@ -90,6 +90,20 @@ __device__ __forceinline__ T mpk_row(T sum, T xo, T xp, bool has_prev,
   return v / gamma;
 }
 
+// Fixed-order sum of q over the workgroup's lanes (wavefront tree, then the
+// wavefronts in order), written to part[blockIdx.x].
+__device__ __forceinline__ void block_partial(double q, double* part) {
+  __shared__ double red[kSlicesPerBlock];
+  for (int off = kWave / 2; off > 0; off >>= 1) q += __shfl_xor(q, off);
+  if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = q;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kSlicesPerBlock; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
 // x, xprev and y are columns of a block of vectors with layout XV (row r of
 // a column at column base + XV.row_off(r)); the plain and residual
 // epilogues use contiguous vectors (column-major view).  The matrix
@@ -98,9 +112,11 @@ __device__ __forceinline__ T mpk_row(T sum, T xo, T xp, bool has_prev,
 // x.  GATED: the launch does nothing unless *gate == expect.  Both are
 // separate instantiations: the few extra argument loads and waits at the
 // start of every wavefront cost the other launches 3-5% on a 7-point
-// stencil, whose wavefronts are short.
+// stencil, whose wavefronts are short.  NORM (EPI_MPK): the workgroup's
+// partial sum of y^2 (of the stored values, in float64) goes to
+// part[blockIdx.x], the fused square-sum epilogue of the basis vectors.
 template <typename T, int EPI, typename IDX, bool GATED = false,
-          bool PREC = false>
+          bool PREC = false, bool NORM = false>
 __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
     const int64_t* __restrict__ ptr, const int32_t* __restrict__ width,
     const IDX* __restrict__ col, const int32_t* __restrict__ kbase,
@@ -154,23 +170,19 @@ __global__ __launch_bounds__(kSpmvBlock) void k_spmv(
   if constexpr (EPI == EPI_PLAIN) {
     if (r < n) y[r] = sum;
   } else if constexpr (EPI == EPI_MPK) {
-    if (r < n) y[ro] = mpk_row<T>(sum, xo, xp, xprev != nullptr, rec, j);
+    T yv = 0;
+    if (r < n) {
+      yv = mpk_row<T>(sum, xo, xp, xprev != nullptr, rec, j);
+      y[ro] = yv;
+    }
+    if constexpr (NORM) block_partial((double)yv * (double)yv, part);
   } else {  // EPI_RESID (float64): r = b - A x, partial sums of r^2
     double rr = 0.0;
     if (r < n) {
       rr = bb - (double)sum;
       y[r] = (T)rr;
     }
-    double q = rr * rr;
-    for (int off = kWave / 2; off > 0; off >>= 1) q += __shfl_xor(q, off);
-    __shared__ double red[kSlicesPerBlock];
-    if (lane == 0) red[threadIdx.x / kWave] = q;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double t = 0.0;
-      for (int w = 0; w < kSlicesPerBlock; ++w) t += red[w];
-      part[blockIdx.x] = t;
-    }
+    block_partial(rr * rr, part);
   }
 }
 
@@ -235,6 +247,22 @@ inline unsigned spmv_grid(const Sell& S) {
 inline int xcd_contig(const Sell& S, int vbytes) {
   const int64_t bytes = S.nnz_padded * (vbytes + (S.rcol ? 2 : 4));
   return bytes <= ((int64_t)192 << 20) ? 1 : 0;
+}
+
+// out[0] = the fixed-order sum of part[0:np].
+__global__ __launch_bounds__(1024) void k_sum_partials(const double* part,
+                                                       int64_t np,
+                                                       double* out) {
+  __shared__ double red[1024];
+  double t = 0.0;
+  for (int64_t i = threadIdx.x; i < np; i += 1024) t += part[i];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
 }
 
 __global__ __launch_bounds__(1024) void k_reduce_norm(const double* part,
@@ -354,6 +382,33 @@ void spmv_mpk(const Sell& S, const T* val, QView<T> Q, int jx, int jprev,
 #undef SGM_SPMV
   SGM_CHECK_LAUNCH();
 }
+
+template <typename T>
+void spmv_mpk_norm(const Sell& S, const T* val, QView<T> Q, int jx, int jprev,
+                   int jy, const double* rec, int j, double* part,
+                   double* norm2, hipStream_t st) {
+  const T* xp = jprev >= 0 ? (const T*)Q.col(jprev) : (const T*)nullptr;
+#define SGM_SPMV(IDX, colp)                                                   \
+  hipLaunchKernelGGL((k_spmv<T, EPI_MPK, IDX, false, false, true>),           \
+                     dim3(spmv_grid(S)), dim3(kSpmvBlock), 0, st, S.ptr,      \
+                     S.width, colp, S.kbase, val, Q, (const T*)Q.col(jx), Q,  \
+                     (const T*)Q.col(jx), xp, Q.col(jy),                      \
+                     (const double*)nullptr, part, S.n, S.nslices, rec, j,    \
+                     xcd_contig(S, (int)sizeof(T)), (const int*)nullptr, 0)
+  if (S.rcol) SGM_SPMV(int16_t, S.rcol); else SGM_SPMV(int32_t, S.col);
+#undef SGM_SPMV
+  SGM_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(1024), 0, st,
+                     (const double*)part, (int64_t)spmv_grid(S), norm2);
+  SGM_CHECK_LAUNCH();
+}
+
+template void spmv_mpk_norm<double>(const Sell&, const double*, QView<double>,
+                                    int, int, int, const double*, int,
+                                    double*, double*, hipStream_t);
+template void spmv_mpk_norm<float>(const Sell&, const float*, QView<float>,
+                                   int, int, int, const double*, int, double*,
+                                   double*, hipStream_t);
 
 // Depth-k matrix powers kernel (temporal blocking).  The rows are cut into
 // slabs of at least the matrix bandwidth h (|column - row| <= h), so step

@@ -104,6 +104,62 @@ def test_mpk_scaled_newton_with_complex_pair(lib):
         assert err <= 1e-13 * (j + 1), (j, err)
 
 
+@pytest.mark.parametrize("precision,mk,ragged", [
+    ("fp64", lambda: W.conv_diff_2d(40, 10.0), False),
+    ("fp32_ir", lambda: W.conv_diff_2d(40, 10.0), False),
+    # n = 27^3 = 19,683: not a multiple of 64 (a partial last slice and a
+    # partial last workgroup of partial sums)
+    ("fp64", lambda: W.poisson_3d(27), True)])
+def test_mpk_norms_epilogue(lib, precision, mk, ragged):
+    """sgm_mpk_norms: the fused square-sum epilogue of the matrix powers
+    kernel.  Its columns are bitwise those of sgm_mpk; its sums match the
+    float64 sums of squares of the stored columns (to float64 rounding of
+    a reordered sum) and, in float64, the oracle's basis vectors' norms."""
+    import torch
+    A = mk()
+    M = csr(A)
+    n, ld, s = A.n, ((A.n + 63) // 64) * 64, 9
+    assert (n % 64 != 0) == ragged
+    rng = np.random.default_rng(5)
+    q = rng.standard_normal(n)
+    q /= np.linalg.norm(q)
+    ritz = np.array([7.5, 2.0 + 1.0j, 2.0 - 1.0j, 0.5, 5.0, 3.0 + 0.25j,
+                     3.0 - 0.25j, 1.0, 6.0])
+    sh = o.newton_shifts(o.leja_order(ritz), scaled=True)
+    rec = np.stack([sh.theta, sh.gamma, sh.delta], 1)
+    Q0 = np.zeros((n, s + 1))
+    Q0[:, 0] = q
+    dt = np.float64 if precision == "fp64" else np.float32
+    Qa = flat_cols(torch, Q0.astype(dt), ld)
+    Qb = flat_cols(torch, Q0.astype(dt), ld)
+    G = lib.Matrix.from_csr(A)
+    lib.mpk(G, Qa, ld, 0, s, rec, precision=precision)
+    nrm2 = lib.mpk_norms(G, Qb, ld, 0, s, rec, precision=precision)
+    assert torch.equal(Qa, Qb)
+    Vg = cols_of(Qb, n, ld, s + 1)[:, 1:].astype(np.float64)
+    ref = np.sum(Vg * Vg, axis=0)
+    assert nrm2.shape == (s,)
+    assert np.all(np.abs(nrm2 - ref) <= 1e-13 * ref)
+    if precision == "fp64":
+        V = o._Engine(M, o.Options()).mpk(q, sh, s)
+        vn = np.sum(V * V, axis=0)
+        # the columns agree to 1e-13 (j + 1) relative (the test above)
+        assert np.all(np.abs(nrm2 - vn) <= 1e-12 * np.arange(1, s + 1) * vn)
+    # invalid input: a work array shorter than ceil(n / 256)
+    work = torch.empty((n + 255) // 256 - 1, dtype=torch.float64,
+                       device="cuda")
+    out = torch.empty(s, dtype=torch.float64, device="cuda")
+    rec_d = torch.tensor(rec.ravel(), device="cuda")
+    import ctypes as C
+    rc = lib.lib().sgm_mpk_norms(G.handle, 0, lib.PRECISION[precision],
+                                 C.c_void_p(Qb.data_ptr()), ld, 0, s,
+                                 C.c_void_p(rec_d.data_ptr()), s,
+                                 C.c_void_p(out.data_ptr()),
+                                 C.c_void_p(work.data_ptr()), work.numel(),
+                                 None)
+    assert rc == lib.EINVAL
+
+
 # ------------------------------------------------------------------ block QR
 
 def _basis_and_block(A, i, s, seed=2, basis="scaled_newton"):
