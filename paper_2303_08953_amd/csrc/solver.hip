@@ -1307,6 +1307,11 @@ sgm_status sgm_solve(sgm_matrix A, const double* b, const double* x0,
   } catch (const Error& e) {
     st = e.st;
     err = e.msg;
+    // launches queued behind the failed step (matrix powers steps queued
+    // ahead, gated off by the tail) still read the workspace: let them
+    // finish before the caller may release it
+    (void)hipStreamSynchronize(as_stream(stream));
+    (void)hipGetLastError();
   }
   if (res_hist)
     for (int32_t i = 0; i < res_cap && i < (int32_t)R.res_hist.size(); ++i)

@@ -198,3 +198,30 @@ def test_solve_on_a_side_stream(lib):
     assert r.status == lib.OK
     assert np.array_equal(x.cpu().numpy(), ref.x.cpu().numpy())
     assert list(r.s_hist) == list(ref.s_hist)
+
+
+def test_non_finite_matrix_ends_the_solve(lib):
+    """A NaN in the matrix ends the solve with the numerical-breakdown
+    status inside the first block, which (with the shifts given, no
+    pre-phase) already has the next block's matrix powers steps queued
+    behind it; they are gated off on the device and the call returns
+    after them, so the same workspace then serves a clean solve that is
+    bitwise a fresh one."""
+    A = W.conv_diff_2d(64, 10.0)
+    b = W.rhs(A.n, 1)
+    shifts = np.linspace(0.2, 7.8, 8)
+    kw = dict(s_max=8, restart=64, tol=1e-10, shifts=shifts,
+              use_estimator=False)
+    val = np.array(A.val, dtype=np.float64)
+    val[val.size // 2] = np.nan
+    ws = lib.Workspace()
+    G = lib.Matrix(A.n, A.row_ptr, A.col, val)
+    with pytest.raises(lib.SgmError) as e:
+        lib.solve(G, b, workspace=ws, **kw)
+    assert e.value.status == lib.ENUMERIC
+    G.update_values(np.array(A.val, dtype=np.float64))
+    r = lib.solve(G, b, workspace=ws, **kw)
+    ref = lib.solve(lib.Matrix.from_csr(A), b, **kw)
+    assert r.status == lib.OK and ref.status == lib.OK
+    assert np.array_equal(r.x.cpu().numpy(), ref.x.cpu().numpy())
+    assert list(r.s_hist) == list(ref.s_hist)
