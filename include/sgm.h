@@ -14,7 +14,8 @@
  *  - All GPU work is enqueued on `stream` (a hipStream_t passed as void*;
  *    NULL means the default stream).  Entry points that return host-visible
  *    results (sgm_solve, sgm_block_orth, sgm_shifts) synchronise `stream`
- *    before returning; the others return after enqueueing.
+ *    before returning, on their error returns too (SGM_EINVAL aside, which
+ *    enqueues nothing); the others return after enqueueing.
  *  - The caller owns every buffer it passes.  The library allocates device
  *    memory only in sgm_matrix_create (the analysed copies of the matrix)
  *    and sgm_matrix_ilu0 (its ILU(0) factors) and frees it in
