@@ -914,6 +914,27 @@ Handle* handle(sgm_matrix A) { return reinterpret_cast<Handle*>(A); }
     return SGM_EHIP;                                                       \
   }
 
+// The same for the entry points that synchronise their stream: an error
+// after launches were queued waits for them before returning, so the
+// caller may release the buffers they use.
+#define SGM_API_END_SYNC(stream)                                           \
+  }                                                                        \
+  catch (const Error& e) {                                                 \
+    set_error(e.msg);                                                      \
+    if (e.st != SGM_EINVAL) drain(stream);                                 \
+    return e.st;                                                           \
+  }                                                                        \
+  catch (const std::exception& e) {                                        \
+    set_error(e.what());                                                   \
+    drain(stream);                                                         \
+    return SGM_EHIP;                                                       \
+  }                                                                        \
+  catch (...) {                                                            \
+    set_error("unknown error");                                            \
+    drain(stream);                                                         \
+    return SGM_EHIP;                                                       \
+  }
+
 void validate_opts(const sgm_opts* o) {
   SGM_REQUIRE(o != nullptr, "opts is NULL");
   SGM_REQUIRE(o->s_max >= 1 && o->s_max <= 256, "s_max must be in [1, 256]");
@@ -973,6 +994,12 @@ size_t solve_ws_bytes(const Matrix& M, const sgm_opts& o) {
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// waits for the stream without throwing, and clears the sticky error
+void drain(void* stream) {
+  (void)hipStreamSynchronize(as_stream(stream));
+  (void)hipGetLastError();
+}
 
 // Workspace of the stand-alone block orthogonalisation.
 void block_layout(Arena& a, Work& w, int i, int s, int64_t n_rows) {
@@ -1310,8 +1337,7 @@ sgm_status sgm_solve(sgm_matrix A, const double* b, const double* x0,
     // launches queued behind the failed step (matrix powers steps queued
     // ahead, gated off by the tail) still read the workspace: let them
     // finish before the caller may release it
-    (void)hipStreamSynchronize(as_stream(stream));
-    (void)hipGetLastError();
+    drain(stream);
   }
   if (res_hist)
     for (int32_t i = 0; i < res_cap && i < (int32_t)R.res_hist.size(); ++i)
@@ -1340,7 +1366,7 @@ sgm_status sgm_solve(sgm_matrix A, const double* b, const double* x0,
   }
   if (st < 0) set_error(err);
   return st;
-  SGM_API_END
+  SGM_API_END_SYNC(stream)
 }
 
 sgm_status sgm_grad_vals(sgm_matrix A, const double* lambda, const double* x,
@@ -1478,7 +1504,7 @@ sgm_status sgm_block_orth(sgm_precision precision, int64_t n_rows, void* Q,
   run_block_orth(precision, Q, ldq, i, s, omega, orth, w, as_stream(stream),
                  p, R_top, R_kk);
   return SGM_OK;
-  SGM_API_END
+  SGM_API_END_SYNC(stream)
 }
 
 sgm_status sgm_block_orth_noalloc(sgm_precision precision, int64_t n_rows,
@@ -1498,7 +1524,7 @@ sgm_status sgm_block_orth_noalloc(sgm_precision precision, int64_t n_rows,
   run_block_orth(precision, Q, ldq, i, s, omega, orth, w, as_stream(stream),
                  p, R_top, R_kk);
   return SGM_OK;
-  SGM_API_END
+  SGM_API_END_SYNC(stream)
 }
 
 size_t sgm_shifts_ws_size(int32_t m0) {
@@ -1553,7 +1579,7 @@ sgm_status sgm_shifts(const double* H, int32_t ldh, int32_t m0,
   if (info[0] != 0 || info[3] != 0)
     throw Error{SGM_ENUMERIC, "QR iteration failed or non-finite Ritz values"};
   return SGM_OK;
-  SGM_API_END
+  SGM_API_END_SYNC(stream)
 }
 
 const char* sgm_status_string(sgm_status s) {
