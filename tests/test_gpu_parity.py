@@ -241,6 +241,44 @@ def test_shifts_match_oracle_on_arnoldi_hessenberg(lib):
     assert s0 == s0r
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 64, 65, 129, 200, 201, 256, 300,
+                               513])
+def test_francis_qr_orders(lib, n):
+    """The GPU Francis QR (Sec. 3.4's Ritz values) at orders covering every
+    storage and lane-chunk case (packed in LDS up to order 200, global
+    scratch above; one to sixteen 64-lane chunks) against the exact
+    spectrum: a normal matrix with real eigenvalues and complex pairs,
+    reduced to Hessenberg form, so that every eigenvalue is perfectly
+    conditioned."""
+    import scipy.linalg as sl
+    rng = np.random.default_rng(n)
+    D = np.zeros((n, n))
+    ev = []
+    i = 0
+    while i < n:
+        if i + 1 < n and rng.random() < 0.4:
+            a, b = rng.uniform(0.5, 4.0), rng.uniform(0.1, 2.0)
+            D[i:i + 2, i:i + 2] = [[a, b], [-b, a]]
+            ev += [a + 1j * b, a - 1j * b]
+            i += 2
+        else:
+            D[i, i] = rng.uniform(-1.0, 4.0)
+            ev.append(D[i, i] + 0j)
+            i += 1
+    ev = np.array(ev)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    H = sl.hessenberg(Q @ D @ Q.T)
+    H = np.triu(H, -1)
+    ritz, rec, s0, hits = lib.shifts(H, n)
+    assert ritz.shape == (n,)
+    d1 = max(np.abs(ev - z).min() for z in ritz)
+    d2 = max(np.abs(ritz - z).min() for z in ev)
+    assert max(d1, d2) <= 1e-11 * np.abs(ev).max(), (d1, d2)
+    # conjugate pairs come out exactly conjugate
+    im = ritz.imag[ritz.imag != 0.0]
+    assert np.isclose(im.sum(), 0.0, atol=1e-12 * np.abs(ev).max())
+
+
 @pytest.mark.parametrize("lmax,case", [(200.0, "uniform_200"),
                                        (2000.0, "max_2000")])
 def test_estimator_on_gpu_matches_oracle(lib, lmax, case):
