@@ -151,6 +151,48 @@ def test_poisson128_bench_workload(lib):
     spmv_rows_match(A, y, xr, rng.choice(A.n, 2048, replace=False))
 
 
+@pytest.mark.parametrize("precision,orth,prephase", [
+    ("fp64", "bcgs2_pyth", "cgs2"), ("fp64", "bcgs2", "monomial"),
+    ("fp64", "bcgs2_pyth", "monomial"), ("fp32_ir", "bcgs2_pyth", "monomial")])
+def test_poisson128_bench_workload_variants(lib, precision, orth, prephase):
+    """The bench system under the options built beside the paper's method
+    (Pythagorean second pass, monomial-block pre-phase, both; float64 and
+    float32-IR), against the oracle's stored classical solve.  Each cycle
+    still minimises the residual over the same Krylov space, so at the same
+    iteration count the float64 iterates agree to rounding:
+    - float64: true residual <= 1e-10, iterations within +-s_max of the
+      oracle's, x within 1e-8 relative on the sampled entries; with the
+      column-wise pre-phase the block sizes are the oracle's;
+    - float32-IR: true residual <= 1e-10 and x within kappa(A)
+      (r_gpu + r_oracle) of the oracle's x."""
+    g = oracle_golden("poisson3d_128_oracle.npz")
+    A = W.poisson_3d(128)
+    M = csr(A)
+    b = W.rhs(A.n, 2)
+    G = lib.Matrix.from_csr(A)
+    kw = dict(s_max=32, restart=128, tol=1e-10, max_restarts=1000, orth=orth,
+              prephase=prephase, prephase_s=8, precision=precision)
+    if precision == "fp32_ir":
+        kw.update(inner_tol=1e-6, max_outer=500)
+    r = lib.solve(G, b, **kw)
+    x = r.x.cpu().numpy()
+    assert r.status == lib.OK
+    true = np.linalg.norm(b - M @ x) / np.linalg.norm(b)
+    assert true <= 1e-10
+    idx, xs_ref = g["sample_idx"], g["x_samples"]
+    err = np.linalg.norm(x[idx] - xs_ref) / np.linalg.norm(xs_ref)
+    if precision == "fp64":
+        assert abs(r.info["iters"] - int(g["iters"])) <= 32
+        assert err <= 1e-8, err
+        if prephase == "cgs2":
+            assert list(r.s_hist) == g["s_hist"].tolist()
+    else:
+        bound = poisson3d_kappa(128) * (true + float(g["rel_res_true"]))
+        assert err <= bound, (err, bound)
+    print(f"poisson3d_128 {precision} {orth} {prephase}: error vs oracle "
+          f"{err:.2e}, {r.info['iters']} iterations")
+
+
 def test_varcd192_jacobi_first_cycle(lib):
     """3D variable-coefficient convection-diffusion 192^3 with right Jacobi,
     s_max 128, restart 256: one float64 cycle.  The first 8 residuals equal
