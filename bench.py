@@ -80,8 +80,8 @@ def spmv_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_hash):
-    p = os.path.join(ROOT, "profiles", "spmv_poisson3d_128_traffic.json")
+def load_traffic(kernel_hash, name="spmv_poisson3d_128_traffic.json"):
+    p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
     with open(p) as f:
@@ -840,6 +840,13 @@ def main():
         # the same figure for the float32 inner solves' SpMV
         out["roofline_fp32"] = spmv_roofline(A, G, infos["fp32_ir"], 4,
                                              "float")
+        r32 = out["roofline_fp32"]
+        if r32 is not None and args.nx == 128:
+            t32 = load_traffic(spmv_source_hash(),
+                               "spmv_poisson3d_128_fp32_traffic.json")
+            r32["traffic"] = t32
+            r32["traffic_gbs"] = (round(t32 / (r32["avg_launch_us"] * 1e-6)
+                                        / 1e9, 1) if t32 else None)
     gold = oracle_samples(args.nx)
     if gold is not None:
         # error of each mode's solution against the oracle's float64 solve
